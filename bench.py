@@ -1,0 +1,184 @@
+"""Benchmark: Ewald energy + forces throughput on one MI355X.
+
+Workload: rock-salt lattice of 32^3 sites (N = 32768, L = 32, spacing 1,
+charges +-1, jitter U(-0.1, 0.1)), alpha = 0.7, r_c = 4.5, k_max = 20 -- the
+32^3 NaCl crystal of the paper's strong-scaling study (section 4.2) in reduced
+units.  One step = one complete ewald_energy_forces call (binning, cell list,
+real-space pairs, phase tables, structure factor, reduction, force gather,
+totals) with inputs resident in HBM.
+
+Prints one JSON line: the mixed-precision throughput as ``value`` (particle
+evaluations per second), the plain-FP64 throughput beside it, p50/p99 latency,
+errors of both paths against the FP64 CPU oracle, the roofline of the dominant
+kernel (per-kernel HIP-event timing on the plan's stream) and the oracle's own
+throughput on this host.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Ewald E+F particle-evals/s, mixed vs FP64 at 1e-6 rel force err; p99 latency"
+WORKLOAD = "rocksalt32"
+
+# Algorithmic flops per unit (one particle x one k vector of the half space),
+# counted for a direct evaluation: structure factor 10 (complex phase product 6,
+# charge-weighted complex accumulate 4); force gather 20 (phase 6, Re/Im of
+# exp(i k.r) conj(G) 6, force accumulate 6, potential 2).  Real space: 30 per
+# ordered pair inside the cutoff (plus three special functions).
+FLOPS_PER_UNIT = {"sk": 10.0, "gather": 20.0}
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}  # published MI355X vector peaks (FP64, FP32)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--latency-calls", type=int, default=300)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD)
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    return ap.parse_args()
+
+
+def time_steps(plan, pos, q, out, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        plan.energy_forces(pos, q, True, False, out=out)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(s)
+    for _ in range(steps):
+        plan.energy_forces(pos, q, True, False, out=out)
+    t1.record(s)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def kernel_profile(plan, pos, q, out, steps):
+    import torch
+    plan.profile_reset()
+    plan.profile(True)
+    for _ in range(steps):
+        plan.energy_forces(pos, q, True, False, out=out)
+    torch.cuda.synchronize()
+    prof = plan.profile_read()
+    plan.profile(False)
+    return {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1]} for k, v in prof.items()}
+
+
+def latencies(plan, pos, q, out, calls):
+    import torch
+    lat = []
+    for _ in range(calls):
+        t = time.perf_counter()
+        plan.energy_forces(pos, q, True, False, out=out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat.sort()
+    return {"p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+            "calls": calls}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU sharding is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1708_01135_amd import ewald, workloads
+
+    sysm = workloads.make_config(args.workload, 0)
+    n = sysm.n
+    dev = torch.device("cuda:0")
+    pos = torch.tensor(sysm.pos, dtype=torch.float64, device=dev)
+    q = torch.tensor(sysm.q, dtype=torch.float64, device=dev)
+    nk = ewald.kset_size(sysm.k_max)
+    results = {}
+    precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    for prec in precisions:
+        plan = ewald.Plan(n, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, prec)
+        out = (torch.empty(5, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
+               torch.empty(n, dtype=torch.float64, device=dev))
+        ms = time_steps(plan, pos, q, out, args.steps, args.warmup)
+        e, f, _ = plan.energy_forces(pos, q, True, True)
+        torch.cuda.synchronize()
+        assert plan.status() == ewald.OK
+        kp = kernel_profile(plan, pos, q, out, args.steps)
+        lat = latencies(plan, pos, q, out, args.latency_calls)
+        results[prec] = dict(ms=ms, pe_s=n / (ms * 1e-3), energy=e.cpu().numpy(), forces=f.cpu().numpy(),
+                             kernels=kp, latency=lat)
+        plan.release()
+
+    # errors against the FP64 CPU oracle, and the oracle's own rate on this host
+    cpu = None
+    errs = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        reps, t_tot, ref = 0, 0.0, None
+        while reps < 3 or (t_tot < 10.0 and reps < 20):
+            t = time.perf_counter()
+            ref = oracle.energy_forces(sysm.pos, sysm.q, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, oracle.FAST)
+            t_tot += time.perf_counter() - t
+            reps += 1
+        t_one = t_tot / reps
+        cpu = {"value": n / t_one, "unit": "particle-evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"{reps} full FP64 oracle evaluations (energy, forces, dE/dq) of the same "
+                         f"{n}-ion workload, mean {t_one:.3f} s each"}
+        for prec, r in results.items():
+            ef, ff = r["energy"], r["forces"]
+            errs[prec] = {"rel_E": abs(ef[0] - ref[0][0]) / abs(ref[0][0]),
+                          "rel_F": float(np.linalg.norm(ff - ref[1]) / np.linalg.norm(ref[1]))}
+
+    head = results.get("mixed") or results.get("fp64")
+    head_prec = "mixed" if "mixed" in results else "fp64"
+    kern = head["kernels"]
+    dom = max(("sk", "gather", "pair"), key=lambda k: kern.get(k, {}).get("avg_ms", 0.0))
+    roof = None
+    if dom in FLOPS_PER_UNIT:
+        flops = FLOPS_PER_UNIT[dom] * n * nk
+        ach = flops / (kern[dom]["avg_ms"] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_TFLOPS[head_prec], "unit": "TFLOP/s",
+                "frac": ach / PEAK_TFLOPS[head_prec], "traffic": None, "avg_ms": kern[dom]["avg_ms"]}
+    line = {
+        "metric": METRIC,
+        "value": head["pe_s"],
+        "unit": "particle-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head_prec == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: rock-salt {round(n ** (1 / 3))}^3 N={n} L={sysm.box_L:g} "
+                               f"alpha={sysm.alpha} r_c={sysm.r_c} k_max={sysm.k_max} |K+|={nk}",
+                   "n": n, "precision": head_prec},
+        "latency": head["latency"],
+        "fp64": None if "fp64" not in results else {
+            "value": results["fp64"]["pe_s"], "ms_per_step": results["fp64"]["ms"],
+            "latency": results["fp64"]["latency"]},
+        "mixed_over_fp64": (results["mixed"]["pe_s"] / results["fp64"]["pe_s"]) if len(results) == 2 else None,
+        "errors_vs_oracle": errs or None,
+        "kernels_ms": {p: {k: round(v["avg_ms"], 5) for k, v in r["kernels"].items()} for p, r in results.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

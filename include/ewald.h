@@ -1,0 +1,169 @@
+/*
+ * ewald.h -- C ABI of the MI355X (gfx950) classical Ewald summation library.
+ *
+ * The library evaluates the electrostatic energy, the forces and the
+ * potentials (dE/dq) of N point charges in a periodic cube, split as in
+ * Saunders, Grant & Mueller, "Long range forces in a performance portable
+ * Molecular Dynamics framework" (section 3):
+ *
+ *   real space (section 3.1.1, truncated as in Eq. short_range_force):
+ *       E_real = 1/2 sum_i sum_{(j,s) != (i,0), |d| < r_c} q_i q_j erfc(sqrt(alpha)|d|)/|d|,
+ *       d = r_i - r_j + s, s in L Z^3 (every image closer than r_c, also when r_c > L/2)
+ *   reciprocal space (section 3.1.2, factorised as in Eq. perf_mod1, Algorithms 1 and 2):
+ *       S_k = sum_j q_j exp(i k.r_j),  k = 2 pi n / L,  n in K = {n != 0 : |n|^2 <= k_max^2}
+ *       C_k = 4 pi / (V k^2) exp(-k^2 / (4 alpha)),  E_recip = 1/2 sum_K C_k |S_k|^2
+ *       F_recip,i = q_i sum_K C_k k Im(exp(i k.r_i) conj(S_k))
+ *   self term (section 3.2.2; formula not printed there):  E_self = -sqrt(alpha/pi) sum q_i^2
+ *   neutralising background (the paper assumes Q = 0):     E_bg   = -pi Q^2 / (2 V alpha)
+ *
+ * Units are Gaussian (potential q/r, section 2.1).  alpha is the exponent of the
+ * splitting Gaussian exp(-alpha r^2) (section 3.1.1): callers who write the
+ * real-space kernel as erfc(beta r) pass alpha = beta^2.  The boundary at
+ * infinity is conducting (no dipole term).
+ *
+ * Conventions shared by every entry point:
+ *   - All pointers named "device" are HIP device pointers (e.g. torch CUDA/HIP
+ *     tensors' data_ptr()) on the plan's device; "host" pointers are ordinary
+ *     host memory.  All floating-point arrays are IEEE double, C-contiguous.
+ *   - Positions may lie anywhere; they are reduced into [0, L)^3 internally.
+ *     Results are returned in the caller's particle order.
+ *   - Outputs are overwritten, never accumulated into.
+ *   - Calls are stream-ordered and asynchronous on the plan's stream; they
+ *     return after enqueueing the work.  Host-detectable errors return before
+ *     anything is enqueued.  No call aborts the process.
+ *   - A plan is not re-entrant: calls on one plan must not overlap.  Distinct
+ *     plans may be used concurrently on distinct streams.
+ *   - Results are bitwise reproducible for identical inputs, plan and device
+ *     (fixed-order reductions, no floating-point atomics).
+ */
+#ifndef EWALD_MI355X_H
+#define EWALD_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Opaque plan: one (L, alpha, r_c, k_max, n_max, precision, device, stream). */
+typedef struct ewald_plan_s *ewald_plan_t;
+
+/* Status codes.  ewald_status_string() gives a static English description. */
+typedef enum {
+    EWALD_OK = 0,
+    EWALD_ERR_INVALID_ARG = -1,   /* a parameter or pointer is invalid            */
+    EWALD_ERR_CAPACITY = -2,      /* n exceeds the plan's n_max                   */
+    EWALD_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed             */
+    EWALD_ERR_DEVICE = -4,        /* a HIP runtime call or kernel launch failed   */
+    EWALD_ERR_NONFINITE = -5      /* a position or charge was NaN or infinite     */
+} ewald_status;
+
+/* Arithmetic of the hot kernels. */
+enum {
+    EWALD_PRECISION_FP64 = 0,  /* every step in IEEE double                          */
+    EWALD_PRECISION_MIXED = 1  /* FP32 phases, pair functions and products; FP64
+                                  displacements, angles, S(k) accumulation across
+                                  particles, per-particle sums and all energies   */
+};
+
+/* Plan parameters.
+ *   n_max      largest N the plan will be called with (>= 1); all workspace is
+ *              sized for it at plan time.
+ *   box_L      side of the periodic cube (> 0).
+ *   alpha      Gaussian splitting exponent (> 0), see above.
+ *   r_c        real-space cutoff, 0 < r_c <= box_L; the test is |d|^2 < r_c^2.
+ *   k_max      reciprocal cutoff on integer vectors, |n|^2 <= k_max^2,
+ *              1 <= k_max <= EWALD_K_MAX_LIMIT.
+ *   precision  EWALD_PRECISION_FP64 or EWALD_PRECISION_MIXED.
+ *   device     HIP device ordinal the plan lives on.
+ *   stream     hipStream_t the work is enqueued on; NULL means the device's
+ *              null stream.  May be changed later with ewald_plan_set_stream().
+ *   flags      reserved, must be 0. */
+typedef struct {
+    int64_t n_max;
+    double box_L;
+    double alpha;
+    double r_c;
+    int32_t k_max;
+    int32_t precision;
+    int32_t device;
+    int32_t flags;
+    void *stream;
+} ewald_params;
+
+#define EWALD_K_MAX_LIMIT 100
+
+/* Static description of a status code (never NULL). */
+const char *ewald_status_string(ewald_status status);
+
+/* Validate parameters without touching the GPU: EWALD_OK or EWALD_ERR_INVALID_ARG. */
+ewald_status ewald_params_validate(const ewald_params *params);
+
+/* Device bytes a plan with these parameters allocates (0 if the parameters
+ * are invalid).  Pure host arithmetic: usable for admission decisions. */
+size_t ewald_plan_workspace_bytes(const ewald_params *params);
+
+/* Number of k vectors in the half space K+ (n_x > 0, or n_x = 0 and n_y > 0,
+ * or n_x = n_y = 0 and n_z > 0) for this k_max; |K| = 2 |K+|.  Host only. */
+int64_t ewald_kset_size(int32_t k_max);
+
+/* Create a plan: validates *params, builds the k-set tables and the cell grid
+ * (n_c = floor(L / r_c) cells per axis) and allocates all device workspace for
+ * n_max.  On success *out receives the plan; on failure *out is set to NULL and
+ * nothing stays allocated.  Errors: INVALID_ARG (bad params or out == NULL),
+ * OUT_OF_MEMORY, DEVICE. */
+ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out);
+
+/* Replace the stream the plan enqueues on (NULL: the null stream). */
+ewald_status ewald_plan_set_stream(ewald_plan_t plan, void *stream);
+
+/* Energy, forces and dE/dq for n charges (section 3, formulas above).
+ *   pos     device, n x 3 row-major (x, y, z per particle); read only.
+ *   q       device, n charges; read only.
+ *   energy  device, 5 doubles written: {total, real, recip, self, background}.
+ *   forces  device, n x 3 row-major F_i = -dE/dr_i, or NULL to skip.
+ *   dEdq    device, n values dE/dq_i, or NULL to skip.
+ * Errors returned immediately: INVALID_ARG (NULL plan/pos/q/energy, n < 1),
+ * CAPACITY (n > n_max), DEVICE (launch failure).  Non-finite inputs are found
+ * on the device: the energy is set to NaN and EWALD_ERR_NONFINITE is latched
+ * for ewald_plan_status(). */
+ewald_status ewald_energy_forces(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
+                                 double *energy, double *forces, double *dEdq);
+
+/* Synchronise the plan's stream, then return and clear the status latched by
+ * device-side checks (EWALD_OK if none). */
+ewald_status ewald_plan_status(ewald_plan_t plan);
+
+/* Synchronise the plan's stream and free everything the plan owns.
+ * ewald_release(NULL) is a no-op; using a plan after release is undefined. */
+void ewald_release(ewald_plan_t plan);
+
+/* ---- inspection hooks (tests, profiling) ---- */
+
+/* Number of k vectors in the plan's half space K+. */
+int64_t ewald_plan_kcount(ewald_plan_t plan);
+
+/* Host copy of the plan's K+ as integer triples (host, kcount x 3 int32), in
+ * the order ewald_debug_copy_sk() uses. */
+ewald_status ewald_debug_kset(ewald_plan_t plan, int32_t *n_xyz);
+
+/* Host copy of S_k over K+ from the last completed evaluation (host arrays of
+ * kcount doubles).  Synchronises the plan's stream. */
+ewald_status ewald_debug_copy_sk(ewald_plan_t plan, double *re, double *im);
+
+/* Kernel timing: when enabled, every launch of the plan is bracketed by HIP
+ * events on the plan's stream and its duration accumulated per kernel class.
+ * ewald_profile_read() synchronises, fills up to max_entries names (static
+ * strings), total milliseconds and launch counts, and returns the number of
+ * kernel classes; ewald_profile_reset() clears the totals. */
+ewald_status ewald_profile_enable(ewald_plan_t plan, int32_t enable);
+int32_t ewald_profile_read(ewald_plan_t plan, const char **names, double *total_ms,
+                           int64_t *launches, int32_t max_entries);
+ewald_status ewald_profile_reset(ewald_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EWALD_MI355X_H */

@@ -1,0 +1,153 @@
+// Internal declarations of the gfx950 Ewald library: plan layout, plain data
+// types shared by the kernels and the host runtime, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ewald.h"
+
+namespace ewk {
+
+// Reciprocal-space work decomposition (see k_recip.hip):
+//   a "row" is one (n_x, n_y) pair of the half space, carrying every n_z with
+//   n_x^2 + n_y^2 + n_z^2 <= K^2, i.e. |n_z| <= m_row;
+//   a "slot" is (row, a = |n_z|) and stands for the two vectors (n_x, n_y, +a) and
+//   (n_x, n_y, -a), whose phases exp(+-i a theta_z) are complex conjugates;
+//   a "segment" is a run of kQ consecutive a values (a = kQ*s ... kQ*s + kQ-1).
+constexpr int kQ = 8;        // a values per segment
+constexpr int kLanes = 64;   // wavefront width on CDNA
+constexpr int kSkWaves = 4;  // waves per structure-factor block (one row group, one segment)
+
+struct alignas(8) c32 {
+    float re, im;
+};
+struct alignas(16) c64 {
+    double re, im;
+};
+template <typename R>
+struct Cplx;
+template <>
+struct Cplx<float> {
+    using type = c32;
+};
+template <>
+struct Cplx<double> {
+    using type = c64;
+};
+
+// 32-byte record used for sorted particles (x, y, z, q), per-particle partial
+// sums (phi, Fx, Fy, Fz) and structure-factor slots (S+ re, S+ im, S- re, S- im).
+struct alignas(32) d4 {
+    double a, b, c, d;
+};
+
+// Upper bound on the gather's k splits (grid.y) for small particle counts.
+constexpr int kMaxSplit = 16;
+struct SplitTable {
+    int lo[kMaxSplit + 1];
+};
+
+enum KernelClass {
+    KC_BIN = 0,
+    KC_SCAN,
+    KC_SCATTER,
+    KC_CELLSORT,
+    KC_PHASE,
+    KC_SK,
+    KC_SKREDUCE,
+    KC_GATHER,
+    KC_PAIRLIST,
+    KC_PAIR,
+    KC_FINAL_P,
+    KC_FINAL_E,
+    KC_COUNT
+};
+extern const char *const kKernelClassNames[KC_COUNT];
+
+// ---- kernel launchers (each returns the hipGetLastError() of its launch) ----
+struct CellArgs {
+    int64_t n;
+    double L;
+    int nc;
+    int ncell;
+};
+hipError_t launch_bin(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_of,
+                      int *counts, double *qpart, int *status);
+hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill, int *cell_start,
+                       const double *qpart, int n_qblocks, double *scalars, int *item_cell, int *item_off,
+                       int *n_items);
+hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, const int *cell_start,
+                          int *fill, int *tmp_idx);
+hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, const int *tmp_idx,
+                           const double *pos, const double *q, int *perm, d4 *pq);
+
+struct RecipArgs {
+    int64_t n;
+    double L;
+    int K;        // k_max
+    int KP;       // padded per-particle table length (multiple of kQ, >= K+1)
+    int n_rows;
+    int n_units;
+    int n_items;
+    int n_slots;  // n_units * kQ * kLanes
+};
+template <typename R>
+hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const d4 *pq, typename Cplx<R>::type *tx,
+                        typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
+template <typename R>
+hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, int tile,
+                     const typename Cplx<R>::type *tx, const typename Cplx<R>::type *ty,
+                     const typename Cplx<R>::type *tz, const int *unit_group, const int *unit_seg,
+                     const int *row_nx, const int *row_ny, d4 *part);
+template <typename R>
+hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, const d4 *part,
+                            const int *unit_group, const int *unit_seg, const int *row_nx,
+                            const int *row_ny, const int *row_m, const int *row_item, const double *ck,
+                            d4 *sk, R *rec, double *erec_part);
+template <typename R>
+hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split,
+                         const d4 *pq, const typename Cplx<R>::type *tz, const int *item_nx,
+                         const int *item_ny, const int *item_seg, const R *rec, d4 *gpart);
+
+struct PairArgs {
+    int64_t n;
+    double L;
+    int nc;
+    int ncell;
+    double rc2;
+    double alpha;
+};
+// Real-space neighbour lists: entries are 16-bit (neighbour offset code << 11 |
+// index inside that neighbour cell), list of particle i at list[i * cap ...].
+// Pair work items are (cell, kPairHome consecutive home particles).
+constexpr int kPairHome = 8;
+constexpr int kPairLocalBits = 11;
+constexpr int kPairMaxCell = 1 << kPairLocalBits;  // cells up to 2048 particles use lists
+hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, const int *n_items,
+                            const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
+                            uint16_t *list, int *list_cnt, int cap);
+hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, int max_items, const int *n_items,
+                       const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
+                       const uint16_t *list, const int *list_cnt, int cap, d4 *freal);
+
+struct FinalArgs {
+    int64_t n;
+    double L;
+    double alpha;
+    int n_split;
+    int n_erec;
+};
+hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
+                                     const d4 *freal, const d4 *gpart, const double *scalars,
+                                     double *forces, double *dEdq, double *epart);
+hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const double *epart, int n_epart,
+                                  const double *erec_part, const double *scalars, const int *status,
+                                  double *energy);
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+}  // namespace ewk

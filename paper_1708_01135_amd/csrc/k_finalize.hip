@@ -1,0 +1,124 @@
+// Totals and output (section 3.2.2 for the self term):
+//   F_i      = F_real,i + q_i (2 pi / L) sum_splits g_i            (caller order)
+//   dE/dq_i  = phi_real,i + phi_recip,i - 2 sqrt(alpha/pi) q_i - pi Q / (V alpha)
+//   E_real   = 1/2 sum_i q_i phi_real,i
+//   E_self   = -sqrt(alpha/pi) sum q_i^2,   E_bg = -pi Q^2 / (2 V alpha)
+// All sums run in a fixed order (per-block trees, then one ordered pass).
+#include "ewald_internal.h"
+
+namespace ewk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+__global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alpha, int n_split,
+                                                 const d4 *__restrict__ pq, const int *__restrict__ perm,
+                                                 const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
+                                                 const double *__restrict__ scalars, double *__restrict__ forces,
+                                                 double *__restrict__ dEdq, double *__restrict__ epart)
+{
+    __shared__ double s_e[256];
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double e = 0.0;
+    if (s < n) {
+        const d4 fr = freal[s];
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        for (int sp = 0; sp < n_split; ++sp) {
+            const d4 g = gpart[(size_t)sp * n + s];
+            g0 += g.a;
+            g1 += g.b;
+            g2 += g.c;
+            g3 += g.d;
+        }
+        const double q = pq[s].d;
+        const double kf = q * (2.0 * kPi / L);
+        const int64_t i = perm[s];
+        if (forces) {
+            forces[3 * i] = fr.b + kf * g1;
+            forces[3 * i + 1] = fr.c + kf * g2;
+            forces[3 * i + 2] = fr.d + kf * g3;
+        }
+        if (dEdq) {
+            const double V = L * L * L;
+            dEdq[i] = fr.a + g0 - 2.0 * sqrt(alpha / kPi) * q - kPi * scalars[0] / (V * alpha);
+        }
+        e = 0.5 * q * fr.a;
+    }
+    s_e[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) s_e[threadIdx.x] += s_e[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) epart[blockIdx.x] = s_e[0];
+}
+
+__device__ inline double ordered_block_sum(const double *__restrict__ v, int count, double *sh)
+{
+    const int t = threadIdx.x;
+    const int per = (count + 255) / 256;
+    double a = 0.0;
+    for (int k = t * per; k < (t + 1) * per && k < count; ++k) a += v[k];
+    sh[t] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// status[0]: non-finite flag of this evaluation (set by the binning kernel);
+// it is latched into status[1] and cleared here.
+__global__ __launch_bounds__(256) void k_final_e(int n_epart, const double *__restrict__ epart, int n_erec,
+                                                 const double *__restrict__ erec, double L, double alpha,
+                                                 const double *__restrict__ scalars, int *__restrict__ status,
+                                                 double *__restrict__ energy)
+{
+    __shared__ double sh[256];
+    const double e_real = ordered_block_sum(epart, n_epart, sh);
+    const double e_recip = ordered_block_sum(erec, n_erec, sh);
+    if (threadIdx.x == 0) {
+        const double V = L * L * L;
+        const double Q = scalars[0];
+        const double e_self = -sqrt(alpha / kPi) * scalars[1];
+        const double e_bg = -kPi * Q * Q / (2.0 * V * alpha);
+        double tot = e_real + e_recip + e_self + e_bg;
+        const int bad = status[0];
+        if (bad) {
+            tot = __builtin_nan("");
+            status[1] |= bad;
+            status[0] = 0;
+        }
+        energy[0] = tot;
+        energy[1] = e_real;
+        energy[2] = e_recip;
+        energy[3] = e_self;
+        energy[4] = e_bg;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
+                                     const d4 *freal, const d4 *gpart, const double *scalars, double *forces,
+                                     double *dEdq, double *epart)
+{
+    hipLaunchKernelGGL(k_final_p, dim3(ceil_div(a.n, 256)), dim3(256), 0, s, a.n, a.L, a.alpha, a.n_split, pq, perm,
+                       freal, gpart, scalars, forces, dEdq, epart);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const double *epart, int n_epart,
+                                  const double *erec_part, const double *scalars, const int *status,
+                                  double *energy)
+{
+    hipLaunchKernelGGL(k_final_e, dim3(1), dim3(256), 0, s, n_epart, epart, a.n_erec, erec_part, a.L, a.alpha,
+                       scalars, const_cast<int *>(status), energy);
+    return hipGetLastError();
+}
+
+}  // namespace ewk

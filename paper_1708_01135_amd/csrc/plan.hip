@@ -1,0 +1,715 @@
+// Host runtime of the C ABI declared in include/ewald.h: parameter checks,
+// plan-time tables (k-set layout, C_k, cell grid), one device allocation for
+// all workspace, and the per-call launch sequence on the plan's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "ewald_internal.h"
+
+using namespace ewk;
+
+namespace ewk {
+const char *const kKernelClassNames[KC_COUNT] = {"bin",    "scan",   "scatter",  "cellsort", "phase",  "sk",
+                                                 "sk_reduce", "gather", "pair_list", "pair", "final_p", "final_e"};
+template <typename R>
+size_t sk_smem_bytes(int tile, int K1);
+int bin_blocks(int64_t n);
+}  // namespace ewk
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kMaxCellsPerAxis = 128;
+constexpr int kSkTargetBlocks = 2048;     // structure-factor blocks wanted in flight
+constexpr int kGatherTargetBlocks = 1024; // gather blocks wanted in flight
+constexpr int kMaxChunks = 1024;
+constexpr size_t kSkSmemBudget = 48 * 1024;
+
+// ---------------------------------------------------------- k-set layout
+struct KLayout {
+    int K = 0, KP = 0;
+    int n_rows = 0, n_units = 0, n_items = 0, n_segmax = 0;
+    int64_t kcount = 0;
+    // rows sorted by m (descending): structure-factor lanes
+    std::vector<int> row_nx, row_ny, row_m;
+    std::vector<int> unit_g, unit_s;
+    // gather items: per segment, rows with m >= kQ*s in (nx, ny) order
+    std::vector<int> item_nx, item_ny, item_seg;
+    std::vector<int> row_item;  // [seg * n_rows + row] -> item, or -1
+};
+
+int isqrt_floor(int v)
+{
+    int r = (int)std::floor(std::sqrt((double)v));
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+void build_klayout(int K, KLayout &kl)
+{
+    kl.K = K;
+    kl.KP = ((K + 1 + kQ - 1) / kQ) * kQ;
+    struct Row {
+        int nx, ny, m;
+    };
+    std::vector<Row> nat;  // natural (nx, ny) order of the half space
+    const int K2 = K * K;
+    nat.push_back({0, 0, K});
+    for (int ny = 1; ny <= K; ++ny) nat.push_back({0, ny, isqrt_floor(K2 - ny * ny)});
+    for (int nx = 1; nx <= K; ++nx) {
+        const int M = isqrt_floor(K2 - nx * nx);
+        for (int ny = -M; ny <= M; ++ny) nat.push_back({nx, ny, isqrt_floor(K2 - nx * nx - ny * ny)});
+    }
+    kl.n_rows = (int)nat.size();
+    kl.kcount = 0;
+    for (const Row &r : nat) kl.kcount += (r.nx == 0 && r.ny == 0) ? r.m : 2 * r.m + 1;
+
+    std::vector<int> order(nat.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return nat[a].m > nat[b].m; });
+    std::vector<int> sorted_of_nat(nat.size());
+    kl.row_nx.resize(nat.size());
+    kl.row_ny.resize(nat.size());
+    kl.row_m.resize(nat.size());
+    for (size_t r = 0; r < order.size(); ++r) {
+        const Row &w = nat[order[r]];
+        kl.row_nx[r] = w.nx;
+        kl.row_ny[r] = w.ny;
+        kl.row_m[r] = w.m;
+        sorted_of_nat[order[r]] = (int)r;
+    }
+    kl.n_segmax = K / kQ + 1;
+    const int n_groups = (kl.n_rows + kLanes - 1) / kLanes;
+    kl.unit_g.clear();
+    kl.unit_s.clear();
+    for (int g = 0; g < n_groups; ++g) {
+        const int mmax = kl.row_m[g * kLanes];
+        for (int s = 0; s <= mmax / kQ; ++s) {
+            kl.unit_g.push_back(g);
+            kl.unit_s.push_back(s);
+        }
+    }
+    kl.n_units = (int)kl.unit_g.size();
+    kl.row_item.assign((size_t)kl.n_segmax * kl.n_rows, -1);
+    kl.item_nx.clear();
+    kl.item_ny.clear();
+    kl.item_seg.clear();
+    for (int s = 0; s < kl.n_segmax; ++s)
+        for (size_t i = 0; i < nat.size(); ++i) {
+            if (nat[i].m < s * kQ) continue;
+            kl.row_item[(size_t)s * kl.n_rows + sorted_of_nat[i]] = (int)kl.item_nx.size();
+            kl.item_nx.push_back(nat[i].nx);
+            kl.item_ny.push_back(nat[i].ny);
+            kl.item_seg.push_back(s);
+        }
+    kl.n_items = (int)kl.item_nx.size();
+}
+
+int cells_per_axis(double L, double rc)
+{
+    double f = std::floor(L / rc);
+    int nc = f < 1.0 ? 1 : (f > kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)f);
+    // guard against L/rc rounding just above an integer: h must stay >= rc
+    while (nc > 1 && L / nc < rc) --nc;
+    return nc;
+}
+
+int choose_tile(bool mixed, int K1)
+{
+    for (int t = 64; t >= kSkWaves; t /= 2) {
+        const size_t b = mixed ? sk_smem_bytes<float>(t, K1) : sk_smem_bytes<double>(t, K1);
+        if (b <= kSkSmemBudget) return t;
+    }
+    return kSkWaves;
+}
+
+int sk_chunks(int64_t n, int n_units, int tile)
+{
+    const int64_t by_work = (n + tile - 1) / tile;  // at least one tile per chunk
+    int64_t want = (kSkTargetBlocks + n_units - 1) / n_units;
+    if (want < 1) want = 1;
+    int64_t c = std::min<int64_t>(by_work, want);
+    c = std::min<int64_t>(c, kMaxChunks);
+    return (int)std::max<int64_t>(c, 1);
+}
+
+int gather_split(int64_t n)
+{
+    const int64_t blocks = (n + 255) / 256;
+    int64_t s = (kGatherTargetBlocks + blocks - 1) / blocks;
+    return (int)std::min<int64_t>(std::max<int64_t>(s, 1), kMaxSplit);
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Sizes of every device buffer; shared by the admission query and the plan.
+struct Sizes {
+    size_t cell_of, counts, fill, cell_start, tmp_idx, perm, status;
+    size_t pq, freal, qpart, scalars, epart, erec, ck;
+    size_t tx, part, sk, rec, gpart;
+    size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
+    size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
+    size_t total;
+    int max_chunks;
+    int max_pitems;  // pair work items: cells + n/kPairHome bounds sum_c ceil(count_c / kPairHome)
+    int list_cap;    // neighbour-list entries per particle
+};
+
+// Neighbour-list capacity: 1.5x the expected count inside r_c at the plan's
+// largest density, plus slack; lanes beyond it fall back to the direct loop.
+int pair_list_cap(const ewald_params &p)
+{
+    const double rho = (double)p.n_max / (p.box_L * p.box_L * p.box_L);
+    const double expect = 4.0 / 3.0 * kPi * p.r_c * p.r_c * p.r_c * rho;
+    double cap = 1.5 * expect + 32.0;
+    cap = std::min(cap, (double)p.n_max * 27.0 + 32.0);
+    return (int)std::min(cap, 60000.0);
+}
+
+void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
+{
+    const bool mixed = p.precision == EWALD_PRECISION_MIXED;
+    const int64_t N = p.n_max;
+    const size_t ncell = (size_t)nc * nc * nc;
+    const size_t creal = mixed ? sizeof(c32) : sizeof(c64);
+    const size_t real = mixed ? sizeof(float) : sizeof(double);
+    const int tile = choose_tile(mixed, kl.K + 1);
+    z.max_chunks = sk_chunks(N, kl.n_units, tile);
+    const size_t n_slots = (size_t)kl.n_units * kQ * kLanes;
+    const size_t gcap = std::min<size_t>((size_t)kMaxSplit * N, (size_t)kGatherTargetBlocks * 256 + N);
+    z.cell_of = align_up(sizeof(int) * N);
+    z.counts = align_up(sizeof(int) * ncell);
+    z.fill = align_up(sizeof(int) * ncell);
+    z.cell_start = align_up(sizeof(int) * (ncell + 1));
+    z.tmp_idx = align_up(sizeof(int) * N);
+    z.perm = align_up(sizeof(int) * N);
+    z.status = align_up(sizeof(int) * 2);
+    z.pq = align_up(sizeof(d4) * N);
+    z.freal = align_up(sizeof(d4) * N);
+    z.qpart = align_up(sizeof(double) * 2 * (size_t)bin_blocks(N));
+    z.scalars = align_up(sizeof(double) * 4);
+    z.epart = align_up(sizeof(double) * (size_t)ceil_div(N, 256));
+    z.erec = align_up(sizeof(double) * (size_t)ceil_div((int64_t)n_slots, 256));
+    z.ck = align_up(sizeof(double) * ((size_t)kl.K * kl.K + 1));
+    z.tx = align_up(creal * (size_t)N * kl.KP);
+    z.part = align_up(sizeof(d4) * (size_t)z.max_chunks * n_slots);
+    z.sk = align_up(sizeof(d4) * n_slots);
+    z.rec = align_up(real * (size_t)kl.n_items * kQ * 8);
+    z.gpart = align_up(sizeof(d4) * gcap);
+    z.row_nx = z.row_ny = z.row_m = align_up(sizeof(int) * kl.n_rows);
+    z.unit_g = z.unit_s = align_up(sizeof(int) * kl.n_units);
+    z.row_item = align_up(sizeof(int) * kl.row_item.size());
+    z.item_nx = z.item_ny = z.item_seg = align_up(sizeof(int) * (size_t)std::max(kl.n_items, 1));
+    z.max_pitems = (int)ncell + ceil_div(N, kPairHome);
+    z.list_cap = pair_list_cap(p);
+    z.pitem_cell = z.pitem_off = align_up(sizeof(int) * (size_t)z.max_pitems);
+    z.n_pitems = align_up(sizeof(int));
+    z.plist = align_up(sizeof(uint16_t) * (size_t)z.list_cap * N);
+    z.plist_cnt = align_up(sizeof(int) * N);
+    z.total = 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
+              z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
+              3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx;
+}
+
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct ewald_plan_s {
+    ewald_params prm{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool mixed = false;
+    int nc = 1, ncell = 1;
+    int tile = 4;
+    KLayout kl;
+    Sizes sz{};
+    void *base = nullptr;
+    // device views
+    int *cell_of = nullptr, *counts = nullptr, *fill = nullptr, *cell_start = nullptr, *tmp_idx = nullptr,
+        *perm = nullptr, *status = nullptr;
+    d4 *pq = nullptr, *freal = nullptr, *part = nullptr, *sk = nullptr, *gpart = nullptr;
+    double *qpart = nullptr, *scalars = nullptr, *epart = nullptr, *erec = nullptr, *ck = nullptr;
+    void *tx = nullptr, *ty = nullptr, *tz = nullptr, *rec = nullptr;
+    int *row_nx = nullptr, *row_ny = nullptr, *row_m = nullptr, *unit_g = nullptr, *unit_s = nullptr,
+        *row_item = nullptr, *item_nx = nullptr, *item_ny = nullptr, *item_seg = nullptr;
+    int *pitem_cell = nullptr, *pitem_off = nullptr, *n_pitems = nullptr, *plist_cnt = nullptr;
+    uint16_t *plist = nullptr;
+    // profiling
+    bool prof = false;
+    std::vector<ProfRec> pending;
+    std::vector<hipEvent_t> pool;
+    double tot_ms[KC_COUNT] = {};
+    int64_t launches[KC_COUNT] = {};
+};
+
+namespace {
+
+class DeviceGuard {
+  public:
+    explicit DeviceGuard(int dev)
+    {
+        ok_ = hipGetDevice(&prev_) == hipSuccess;
+        if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+        restore_ = ok_ && prev_ != dev;
+    }
+    ~DeviceGuard()
+    {
+        if (restore_) (void)hipSetDevice(prev_);
+    }
+    bool ok() const { return ok_; }
+
+  private:
+    int prev_ = 0;
+    bool ok_ = false, restore_ = false;
+};
+
+hipEvent_t take_event(ewald_plan_s *p)
+{
+    if (!p->pool.empty()) {
+        hipEvent_t e = p->pool.back();
+        p->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one launcher, bracketed by events when profiling is on.
+template <typename F>
+hipError_t timed(ewald_plan_s *p, int kind, F &&launch)
+{
+    if (!p->prof) return launch();
+    ProfRec r{kind, take_event(p), take_event(p)};
+    if (r.a) (void)hipEventRecord(r.a, p->stream);
+    hipError_t e = launch();
+    if (r.b) (void)hipEventRecord(r.b, p->stream);
+    if (r.a && r.b) p->pending.push_back(r);
+    return e;
+}
+
+void drain_profile(ewald_plan_s *p)
+{
+    for (const ProfRec &r : p->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            p->tot_ms[r.kind] += ms;
+            p->launches[r.kind] += 1;
+        }
+        p->pool.push_back(r.a);
+        p->pool.push_back(r.b);
+    }
+    p->pending.clear();
+}
+
+template <typename T>
+T *carve(char *&cur, size_t bytes)
+{
+    T *r = reinterpret_cast<T *>(cur);
+    cur += bytes;
+    return r;
+}
+
+template <typename T>
+hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t s)
+{
+    if (src.empty()) return hipSuccess;
+    return hipMemcpyAsync(dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ewald_status_string(ewald_status s)
+{
+    switch (s) {
+    case EWALD_OK: return "ok";
+    case EWALD_ERR_INVALID_ARG: return "invalid argument";
+    case EWALD_ERR_CAPACITY: return "n exceeds the plan capacity n_max";
+    case EWALD_ERR_OUT_OF_MEMORY: return "out of memory";
+    case EWALD_ERR_DEVICE: return "HIP device or launch error";
+    case EWALD_ERR_NONFINITE: return "non-finite position or charge";
+    }
+    return "unknown status";
+}
+
+ewald_status ewald_params_validate(const ewald_params *p)
+{
+    if (!p) return EWALD_ERR_INVALID_ARG;
+    if (p->n_max < 1 || p->n_max > ((int64_t)1 << 30)) return EWALD_ERR_INVALID_ARG;
+    if (!(std::isfinite(p->box_L) && p->box_L > 0.0)) return EWALD_ERR_INVALID_ARG;
+    if (!(std::isfinite(p->alpha) && p->alpha > 0.0)) return EWALD_ERR_INVALID_ARG;
+    if (!(std::isfinite(p->r_c) && p->r_c > 0.0 && p->r_c <= p->box_L)) return EWALD_ERR_INVALID_ARG;
+    if (p->k_max < 1 || p->k_max > EWALD_K_MAX_LIMIT) return EWALD_ERR_INVALID_ARG;
+    if (p->precision != EWALD_PRECISION_FP64 && p->precision != EWALD_PRECISION_MIXED) return EWALD_ERR_INVALID_ARG;
+    if (p->device < 0 || p->flags != 0) return EWALD_ERR_INVALID_ARG;
+    return EWALD_OK;
+}
+
+int64_t ewald_kset_size(int32_t k_max)
+{
+    if (k_max < 1 || k_max > EWALD_K_MAX_LIMIT) return 0;
+    int64_t c = 0;
+    const int K2 = k_max * k_max;
+    for (int nx = 0; nx <= k_max; ++nx)
+        for (int ny = -k_max; ny <= k_max; ++ny)
+            for (int nz = -k_max; nz <= k_max; ++nz) {
+                const int m2 = nx * nx + ny * ny + nz * nz;
+                if (m2 == 0 || m2 > K2) continue;
+                if (nx > 0 || (ny > 0) || (ny == 0 && nz > 0)) ++c;
+            }
+    return c;
+}
+
+size_t ewald_plan_workspace_bytes(const ewald_params *p)
+{
+    if (ewald_params_validate(p) != EWALD_OK) return 0;
+    KLayout kl;
+    build_klayout(p->k_max, kl);
+    Sizes z;
+    compute_sizes(*p, kl, cells_per_axis(p->box_L, p->r_c), z);
+    return z.total;
+}
+
+ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
+{
+    if (!out) return EWALD_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (ewald_params_validate(params) != EWALD_OK) return EWALD_ERR_INVALID_ARG;
+    ewald_plan_s *p = new (std::nothrow) ewald_plan_s();
+    if (!p) return EWALD_ERR_OUT_OF_MEMORY;
+    p->prm = *params;
+    p->device = params->device;
+    p->stream = reinterpret_cast<hipStream_t>(params->stream);
+    p->mixed = params->precision == EWALD_PRECISION_MIXED;
+    p->nc = cells_per_axis(params->box_L, params->r_c);
+    p->ncell = p->nc * p->nc * p->nc;
+    build_klayout(params->k_max, p->kl);
+    p->tile = choose_tile(p->mixed, params->k_max + 1);
+    compute_sizes(*params, p->kl, p->nc, p->sz);
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || params->device >= ndev) {
+        delete p;
+        return ndev == 0 ? EWALD_ERR_DEVICE : EWALD_ERR_INVALID_ARG;
+    }
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) {
+        delete p;
+        return EWALD_ERR_DEVICE;
+    }
+    if (hipMalloc(&p->base, p->sz.total) != hipSuccess) {
+        (void)hipGetLastError();
+        delete p;
+        return EWALD_ERR_OUT_OF_MEMORY;
+    }
+    char *cur = static_cast<char *>(p->base);
+    const Sizes &z = p->sz;
+    p->cell_of = carve<int>(cur, z.cell_of);
+    p->counts = carve<int>(cur, z.counts);
+    p->fill = carve<int>(cur, z.fill);
+    p->cell_start = carve<int>(cur, z.cell_start);
+    p->tmp_idx = carve<int>(cur, z.tmp_idx);
+    p->perm = carve<int>(cur, z.perm);
+    p->status = carve<int>(cur, z.status);
+    p->pq = carve<d4>(cur, z.pq);
+    p->freal = carve<d4>(cur, z.freal);
+    p->qpart = carve<double>(cur, z.qpart);
+    p->scalars = carve<double>(cur, z.scalars);
+    p->epart = carve<double>(cur, z.epart);
+    p->erec = carve<double>(cur, z.erec);
+    p->ck = carve<double>(cur, z.ck);
+    p->tx = carve<void>(cur, z.tx);
+    p->ty = carve<void>(cur, z.tx);
+    p->tz = carve<void>(cur, z.tx);
+    p->part = carve<d4>(cur, z.part);
+    p->sk = carve<d4>(cur, z.sk);
+    p->rec = carve<void>(cur, z.rec);
+    p->gpart = carve<d4>(cur, z.gpart);
+    p->row_nx = carve<int>(cur, z.row_nx);
+    p->row_ny = carve<int>(cur, z.row_ny);
+    p->row_m = carve<int>(cur, z.row_m);
+    p->unit_g = carve<int>(cur, z.unit_g);
+    p->unit_s = carve<int>(cur, z.unit_s);
+    p->row_item = carve<int>(cur, z.row_item);
+    p->item_nx = carve<int>(cur, z.item_nx);
+    p->item_ny = carve<int>(cur, z.item_ny);
+    p->item_seg = carve<int>(cur, z.item_seg);
+    p->pitem_cell = carve<int>(cur, z.pitem_cell);
+    p->pitem_off = carve<int>(cur, z.pitem_off);
+    p->n_pitems = carve<int>(cur, z.n_pitems);
+    p->plist = carve<uint16_t>(cur, z.plist);
+    p->plist_cnt = carve<int>(cur, z.plist_cnt);
+
+    // C_k by integer |n|^2 (computed once on the host in FP64)
+    const int K = params->k_max;
+    std::vector<double> ck((size_t)K * K + 1, 0.0);
+    const double L = params->box_L, V = L * L * L, gk = 2.0 * kPi / L;
+    for (int m2 = 1; m2 <= K * K; ++m2) {
+        const double k2 = gk * gk * (double)m2;
+        ck[m2] = 4.0 * kPi / (V * k2) * std::exp(-k2 / (4.0 * params->alpha));
+    }
+    hipError_t e = hipSuccess;
+    const KLayout &kl = p->kl;
+    hipStream_t s = p->stream;
+    if (e == hipSuccess) e = upload(p->ck, ck, s);
+    if (e == hipSuccess) e = upload(p->row_nx, kl.row_nx, s);
+    if (e == hipSuccess) e = upload(p->row_ny, kl.row_ny, s);
+    if (e == hipSuccess) e = upload(p->row_m, kl.row_m, s);
+    if (e == hipSuccess) e = upload(p->unit_g, kl.unit_g, s);
+    if (e == hipSuccess) e = upload(p->unit_s, kl.unit_s, s);
+    if (e == hipSuccess) e = upload(p->row_item, kl.row_item, s);
+    if (e == hipSuccess) e = upload(p->item_nx, kl.item_nx, s);
+    if (e == hipSuccess) e = upload(p->item_ny, kl.item_ny, s);
+    if (e == hipSuccess) e = upload(p->item_seg, kl.item_seg, s);
+    // counters start at zero; afterwards every evaluation leaves them cleared
+    if (e == hipSuccess) e = hipMemsetAsync(p->counts, 0, z.counts, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->fill, 0, z.fill, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->status, 0, z.status, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->sk, 0, z.sk, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(p->base);
+        delete p;
+        return EWALD_ERR_DEVICE;
+    }
+    *out = p;
+    return EWALD_OK;
+}
+
+ewald_status ewald_plan_set_stream(ewald_plan_t plan, void *stream)
+{
+    if (!plan) return EWALD_ERR_INVALID_ARG;
+    plan->stream = reinterpret_cast<hipStream_t>(stream);
+    return EWALD_OK;
+}
+
+ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy,
+                                 double *forces, double *dEdq)
+{
+    if (!p || !pos || !q || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    hipStream_t s = p->stream;
+    const KLayout &kl = p->kl;
+    const double L = p->prm.box_L;
+
+    CellArgs ca{n, L, p->nc, p->ncell};
+    RecipArgs ra{n, L, kl.K, kl.KP, kl.n_rows, kl.n_units, kl.n_items, kl.n_units * kQ * kLanes};
+    PairArgs pa{n, L, p->nc, p->ncell, p->prm.r_c * p->prm.r_c, p->prm.alpha};
+    const int n_chunks = sk_chunks(n, kl.n_units, p->tile);
+    const int chunk_len = (int)((n + n_chunks - 1) / n_chunks);
+    const int n_split = gather_split(n);
+    SplitTable st{};
+    for (int k = 0; k <= n_split; ++k) st.lo[k] = (int)((int64_t)kl.n_items * k / n_split);
+    FinalArgs fa{n, L, p->prm.alpha, n_split, ceil_div((int64_t)ra.n_slots, 256)};
+    const int nqb = bin_blocks(n);
+
+    hipError_t e = hipSuccess;
+    auto run = [&](int kind, auto &&fn) {
+        if (e == hipSuccess) e = timed(p, kind, fn);
+    };
+    run(KC_BIN, [&] { return launch_bin(s, ca, pos, q, p->cell_of, p->counts, p->qpart, p->status); });
+    run(KC_SCAN, [&] {
+        return launch_scan(s, ca, p->counts, p->fill, p->cell_start, p->qpart, nqb, p->scalars, p->pitem_cell,
+                           p->pitem_off, p->n_pitems);
+    });
+    run(KC_SCATTER, [&] { return launch_scatter(s, ca, p->cell_of, p->cell_start, p->fill, p->tmp_idx); });
+    run(KC_CELLSORT, [&] { return launch_cellsort(s, ca, p->cell_start, p->tmp_idx, pos, q, p->perm, p->pq); });
+    if (p->mixed) {
+        auto *tx = static_cast<c32 *>(p->tx), *ty = static_cast<c32 *>(p->ty), *tz = static_cast<c32 *>(p->tz);
+        run(KC_PHASE, [&] { return launch_phase<float>(s, ra, p->pq, tx, ty, tz); });
+        run(KC_SK, [&] {
+            return launch_sk<float>(s, ra, n_chunks, chunk_len, p->tile, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx,
+                                    p->row_ny, p->part);
+        });
+        run(KC_SKREDUCE, [&] {
+            return launch_sk_reduce<float>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
+                                           p->row_m, p->row_item, p->ck, p->sk, static_cast<float *>(p->rec),
+                                           p->erec);
+        });
+        run(KC_GATHER, [&] {
+            return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_nx, p->item_ny, p->item_seg,
+                                        static_cast<const float *>(p->rec), p->gpart);
+        });
+    } else {
+        auto *tx = static_cast<c64 *>(p->tx), *ty = static_cast<c64 *>(p->ty), *tz = static_cast<c64 *>(p->tz);
+        run(KC_PHASE, [&] { return launch_phase<double>(s, ra, p->pq, tx, ty, tz); });
+        run(KC_SK, [&] {
+            return launch_sk<double>(s, ra, n_chunks, chunk_len, p->tile, tx, ty, tz, p->unit_g, p->unit_s,
+                                     p->row_nx, p->row_ny, p->part);
+        });
+        run(KC_SKREDUCE, [&] {
+            return launch_sk_reduce<double>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
+                                            p->row_m, p->row_item, p->ck, p->sk, static_cast<double *>(p->rec),
+                                            p->erec);
+        });
+        run(KC_GATHER, [&] {
+            return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_nx, p->item_ny, p->item_seg,
+                                         static_cast<const double *>(p->rec), p->gpart);
+        });
+    }
+    const int max_pitems = p->ncell + ceil_div(n, kPairHome);
+    run(KC_PAIRLIST, [&] {
+        return launch_pair_list(s, pa, max_pitems, p->n_pitems, p->pitem_cell, p->pitem_off, p->cell_start, p->pq,
+                                p->plist, p->plist_cnt, p->sz.list_cap);
+    });
+    run(KC_PAIR, [&] {
+        return launch_pair(s, pa, p->mixed, max_pitems, p->n_pitems, p->pitem_cell, p->pitem_off, p->cell_start,
+                           p->pq, p->plist, p->plist_cnt, p->sz.list_cap, p->freal);
+    });
+    run(KC_FINAL_P, [&] {
+        return launch_finalize_particles(s, fa, p->pq, p->perm, p->freal, p->gpart, p->scalars, forces, dEdq,
+                                         p->epart);
+    });
+    run(KC_FINAL_E, [&] {
+        return launch_finalize_energy(s, fa, p->epart, ceil_div(n, 256), p->erec, p->scalars, p->status, energy);
+    });
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return EWALD_ERR_DEVICE;
+    }
+    return EWALD_OK;
+}
+
+ewald_status ewald_plan_status(ewald_plan_t p)
+{
+    if (!p) return EWALD_ERR_INVALID_ARG;
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    int st[2] = {0, 0};
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return EWALD_ERR_DEVICE;
+    if (hipMemcpy(st, p->status, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return EWALD_ERR_DEVICE;
+    if (st[1] || st[0]) {
+        const int zero[2] = {0, 0};
+        if (hipMemcpy(p->status, zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess) return EWALD_ERR_DEVICE;
+        return EWALD_ERR_NONFINITE;
+    }
+    return EWALD_OK;
+}
+
+void ewald_release(ewald_plan_t p)
+{
+    if (!p) return;
+    {
+        DeviceGuard dg(p->device);
+        (void)hipStreamSynchronize(p->stream);
+        for (const ProfRec &r : p->pending) {
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        for (hipEvent_t ev : p->pool) (void)hipEventDestroy(ev);
+        if (p->base) (void)hipFree(p->base);
+    }
+    delete p;
+}
+
+int64_t ewald_plan_kcount(ewald_plan_t p) { return p ? p->kl.kcount : 0; }
+
+// k vectors in slot order: for each slot (unit, a-offset, lane) the +a vector,
+// then the -a vector when it belongs to K+.
+static void slot_kvecs(const KLayout &kl, std::vector<int> &kv, std::vector<int64_t> &src)
+{
+    const int n_slots = kl.n_units * kQ * kLanes;
+    kv.clear();
+    src.clear();
+    for (int slot = 0; slot < n_slots; ++slot) {
+        const int lane = slot % kLanes, uq = slot / kLanes, k = uq % kQ, u = uq / kQ;
+        const int r = kl.unit_g[u] * kLanes + lane;
+        if (r >= kl.n_rows) continue;
+        const int a = kl.unit_s[u] * kQ + k;
+        if (a > kl.row_m[r]) continue;
+        const int nx = kl.row_nx[r], ny = kl.row_ny[r];
+        const bool axis = nx == 0 && ny == 0;
+        if (!(axis && a == 0)) {
+            kv.insert(kv.end(), {nx, ny, a});
+            src.push_back(2 * (int64_t)slot);
+        }
+        if (a > 0 && !axis) {
+            kv.insert(kv.end(), {nx, ny, -a});
+            src.push_back(2 * (int64_t)slot + 1);
+        }
+    }
+}
+
+ewald_status ewald_debug_kset(ewald_plan_t p, int32_t *n_xyz)
+{
+    if (!p || !n_xyz) return EWALD_ERR_INVALID_ARG;
+    std::vector<int> kv;
+    std::vector<int64_t> src;
+    slot_kvecs(p->kl, kv, src);
+    for (size_t i = 0; i < kv.size(); ++i) n_xyz[i] = kv[i];
+    return EWALD_OK;
+}
+
+ewald_status ewald_debug_copy_sk(ewald_plan_t p, double *re, double *im)
+{
+    if (!p || !re || !im) return EWALD_ERR_INVALID_ARG;
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    const int n_slots = p->kl.n_units * kQ * kLanes;
+    std::vector<d4> h((size_t)n_slots);
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return EWALD_ERR_DEVICE;
+    if (hipMemcpy(h.data(), p->sk, sizeof(d4) * n_slots, hipMemcpyDeviceToHost) != hipSuccess)
+        return EWALD_ERR_DEVICE;
+    std::vector<int> kv;
+    std::vector<int64_t> src;
+    slot_kvecs(p->kl, kv, src);
+    for (size_t i = 0; i < src.size(); ++i) {
+        const d4 &v = h[src[i] / 2];
+        re[i] = (src[i] & 1) ? v.c : v.a;
+        im[i] = (src[i] & 1) ? v.d : v.b;
+    }
+    return EWALD_OK;
+}
+
+ewald_status ewald_profile_enable(ewald_plan_t p, int32_t enable)
+{
+    if (!p) return EWALD_ERR_INVALID_ARG;
+    p->prof = enable != 0;
+    return EWALD_OK;
+}
+
+int32_t ewald_profile_read(ewald_plan_t p, const char **names, double *total_ms, int64_t *launches,
+                           int32_t max_entries)
+{
+    if (!p) return 0;
+    {
+        DeviceGuard dg(p->device);
+        drain_profile(p);
+    }
+    const int n = std::min<int>(KC_COUNT, max_entries);
+    for (int k = 0; k < n; ++k) {
+        if (names) names[k] = kKernelClassNames[k];
+        if (total_ms) total_ms[k] = p->tot_ms[k];
+        if (launches) launches[k] = p->launches[k];
+    }
+    return KC_COUNT;
+}
+
+ewald_status ewald_profile_reset(ewald_plan_t p)
+{
+    if (!p) return EWALD_ERR_INVALID_ARG;
+    {
+        DeviceGuard dg(p->device);
+        drain_profile(p);
+    }
+    for (int k = 0; k < KC_COUNT; ++k) {
+        p->tot_ms[k] = 0.0;
+        p->launches[k] = 0;
+    }
+    return EWALD_OK;
+}
+
+}  // extern "C"

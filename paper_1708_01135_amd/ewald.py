@@ -1,0 +1,236 @@
+"""Thin ctypes binding of ``libewald_mi355x.so`` (C ABI in ``include/ewald.h``).
+
+Argument marshalling only: every step of the evaluation runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current stream.  If the
+library has not been built, importing the binding raises immediately -- there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libewald_mi355x.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_CAPACITY = -2
+ERR_OUT_OF_MEMORY = -3
+ERR_DEVICE = -4
+ERR_NONFINITE = -5
+
+FP64 = 0
+MIXED = 1
+K_MAX_LIMIT = 100
+
+ENERGY_PARTS = ("total", "real", "recip", "self", "background")
+
+
+class EwaldError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = _lib.ewald_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int64), ("box_L", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("r_c", ctypes.c_double), ("k_max", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python __graft_entry__.py` "
+                          "or `python paper_1708_01135_amd/build.py` (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Params)
+    vp = ctypes.c_void_p
+    lib.ewald_status_string.restype = ctypes.c_char_p
+    lib.ewald_status_string.argtypes = [ctypes.c_int]
+    lib.ewald_params_validate.restype = ctypes.c_int
+    lib.ewald_params_validate.argtypes = [P]
+    lib.ewald_plan_workspace_bytes.restype = ctypes.c_size_t
+    lib.ewald_plan_workspace_bytes.argtypes = [P]
+    lib.ewald_kset_size.restype = ctypes.c_int64
+    lib.ewald_kset_size.argtypes = [ctypes.c_int32]
+    lib.ewald_plan.restype = ctypes.c_int
+    lib.ewald_plan.argtypes = [P, ctypes.POINTER(vp)]
+    lib.ewald_plan_set_stream.restype = ctypes.c_int
+    lib.ewald_plan_set_stream.argtypes = [vp, vp]
+    lib.ewald_energy_forces.restype = ctypes.c_int
+    lib.ewald_energy_forces.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    lib.ewald_plan_status.restype = ctypes.c_int
+    lib.ewald_plan_status.argtypes = [vp]
+    lib.ewald_release.restype = None
+    lib.ewald_release.argtypes = [vp]
+    lib.ewald_plan_kcount.restype = ctypes.c_int64
+    lib.ewald_plan_kcount.argtypes = [vp]
+    lib.ewald_debug_kset.restype = ctypes.c_int
+    lib.ewald_debug_kset.argtypes = [vp, vp]
+    lib.ewald_debug_copy_sk.restype = ctypes.c_int
+    lib.ewald_debug_copy_sk.argtypes = [vp, vp, vp]
+    lib.ewald_profile_enable.restype = ctypes.c_int
+    lib.ewald_profile_enable.argtypes = [vp, ctypes.c_int32]
+    lib.ewald_profile_read.restype = ctypes.c_int32
+    lib.ewald_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
+    lib.ewald_profile_reset.restype = ctypes.c_int
+    lib.ewald_profile_reset.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def library():
+    """The loaded ctypes library (raises ImportError if it was not built)."""
+    return _load()
+
+
+def make_params(n_max, box_L, alpha, r_c, k_max, precision=FP64, device=0, stream=None, flags=0) -> Params:
+    if isinstance(precision, str):
+        precision = {"fp64": FP64, "mixed": MIXED}[precision.lower()]
+    return Params(int(n_max), float(box_L), float(alpha), float(r_c), int(k_max), int(precision),
+                  int(device), int(flags), stream)
+
+
+def validate(params: Params) -> int:
+    return int(_load().ewald_params_validate(ctypes.byref(params)))
+
+
+def workspace_bytes(params: Params) -> int:
+    return int(_load().ewald_plan_workspace_bytes(ctypes.byref(params)))
+
+
+def kset_size(k_max: int) -> int:
+    return int(_load().ewald_kset_size(int(k_max)))
+
+
+def status_string(status: int) -> str:
+    return _load().ewald_status_string(int(status)).decode()
+
+
+def _stream_handle(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Plan:
+    """One Ewald plan: box, splitting, cutoffs, capacity and precision fixed.
+
+    ``energy_forces(pos, q)`` takes float64 device tensors (n,3) and (n,) and
+    returns ``(energy[5], forces or None, dEdq or None)`` as device tensors,
+    enqueued on the current torch stream.
+    """
+
+    def __init__(self, n_max: int, box_L: float, alpha: float, r_c: float, k_max: int,
+                 precision="fp64", device: int = 0):
+        lib = _load()
+        import torch
+        self.device = torch.device("cuda", device)
+        self.params = make_params(n_max, box_L, alpha, r_c, k_max, precision, device,
+                                  _stream_handle(torch.cuda.current_stream(self.device)))
+        h = ctypes.c_void_p()
+        st = lib.ewald_plan(ctypes.byref(self.params), ctypes.byref(h))
+        if st != OK:
+            raise EwaldError(st, "ewald_plan")
+        self._h = h
+
+    @property
+    def handle(self) -> int:
+        if self._h is None:
+            raise RuntimeError("plan was released")
+        return self._h.value
+
+    @property
+    def kcount(self) -> int:
+        return int(_load().ewald_plan_kcount(self.handle))
+
+    def energy_forces(self, pos, q, forces: bool = True, dEdq: bool = False, out=None):
+        import torch
+        lib = _load()
+        n = int(q.shape[0])
+        for name, t, shape in (("pos", pos, (n, 3)), ("q", q, (n,))):
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        if out is None:
+            e = torch.empty(5, dtype=torch.float64, device=pos.device)
+            f = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if forces else None
+            g = torch.empty(n, dtype=torch.float64, device=pos.device) if dEdq else None
+        else:
+            e, f, g = out
+        st = lib.ewald_plan_set_stream(self.handle, _stream_handle())
+        if st != OK:
+            raise EwaldError(st, "ewald_plan_set_stream")
+        st = lib.ewald_energy_forces(self.handle, n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
+                                     f.data_ptr() if f is not None else None,
+                                     g.data_ptr() if g is not None else None)
+        if st != OK:
+            raise EwaldError(st, "ewald_energy_forces")
+        return e, f, g
+
+    def status(self) -> int:
+        return int(_load().ewald_plan_status(self.handle))
+
+    def kset(self):
+        import numpy as np
+        out = np.zeros((self.kcount, 3), dtype=np.int32)
+        st = _load().ewald_debug_kset(self.handle, out.ctypes.data)
+        if st != OK:
+            raise EwaldError(st, "ewald_debug_kset")
+        return out
+
+    def structure_factor(self):
+        import numpy as np
+        re = np.zeros(self.kcount)
+        im = np.zeros(self.kcount)
+        st = _load().ewald_debug_copy_sk(self.handle, re.ctypes.data, im.ctypes.data)
+        if st != OK:
+            raise EwaldError(st, "ewald_debug_copy_sk")
+        return re + 1j * im
+
+    def profile(self, enable: bool = True):
+        _load().ewald_profile_enable(self.handle, int(bool(enable)))
+
+    def profile_read(self) -> Dict[str, Tuple[float, int]]:
+        lib = _load()
+        m = 32
+        names = (ctypes.c_char_p * m)()
+        ms = (ctypes.c_double * m)()
+        cnt = (ctypes.c_int64 * m)()
+        k = lib.ewald_profile_read(self.handle, names, ms, cnt, m)
+        return {names[i].decode(): (float(ms[i]), int(cnt[i])) for i in range(min(k, m))}
+
+    def profile_reset(self):
+        _load().ewald_profile_reset(self.handle)
+
+    def release(self):
+        if getattr(self, "_h", None) is not None:
+            _load().ewald_release(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.release()
+
+
+def energy_forces(pos, q, box_L, alpha, r_c, k_max, precision="fp64", dEdq=False):
+    """One-shot evaluation (builds and releases a plan)."""
+    with Plan(int(q.shape[0]), box_L, alpha, r_c, k_max, precision, pos.device.index or 0) as p:
+        return p.energy_forces(pos, q, True, dEdq)

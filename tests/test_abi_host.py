@@ -1,0 +1,91 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1708_01135_amd import ewald as ew
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ewald.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ewald_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ew.library()
+    names = header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    for st in (0, -1, -2, -3, -4, -5):
+        assert ew.status_string(st)
+    assert "unknown" in ew.status_string(7)
+
+
+BAD = [
+    dict(n_max=0), dict(box_L=0.0), dict(box_L=-1.0), dict(box_L=float("nan")), dict(alpha=0.0),
+    dict(alpha=float("inf")), dict(r_c=0.0), dict(r_c=8.5), dict(k_max=0), dict(k_max=ew.K_MAX_LIMIT + 1),
+    dict(precision=2), dict(device=-1), dict(flags=1),
+]
+
+
+@pytest.mark.parametrize("bad", BAD)
+def test_invalid_parameters_rejected_without_gpu(bad):
+    kw = dict(n_max=512, box_L=8.0, alpha=0.9, r_c=4.0, k_max=8, precision=0, device=0, flags=0)
+    kw.update(bad)
+    p = ew.make_params(**kw)
+    assert ew.validate(p) == ew.ERR_INVALID_ARG
+    assert ew.workspace_bytes(p) == 0
+    h = ctypes.c_void_p(123)
+    assert ew.library().ewald_plan(ctypes.byref(p), ctypes.byref(h)) == ew.ERR_INVALID_ARG
+    assert h.value is None  # *out cleared on failure
+
+
+def test_null_handling():
+    lib = ew.library()
+    p = ew.make_params(512, 8.0, 0.9, 4.0, 8)
+    assert ew.validate(p) == ew.OK
+    assert lib.ewald_plan(ctypes.byref(p), None) == ew.ERR_INVALID_ARG
+    lib.ewald_release(None)  # no-op
+    assert lib.ewald_energy_forces(None, 10, 1, 1, 1, None, None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_plan_status(None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_plan_kcount(None) == 0
+    assert lib.ewald_plan_set_stream(None, None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_debug_copy_sk(None, None, None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_profile_enable(None, 1) == ew.ERR_INVALID_ARG
+
+
+def test_workspace_bytes_scale_with_capacity():
+    small = ew.workspace_bytes(ew.make_params(1000, 8.0, 0.9, 4.0, 8))
+    big = ew.workspace_bytes(ew.make_params(100000, 8.0, 0.9, 4.0, 8))
+    mixed = ew.workspace_bytes(ew.make_params(100000, 8.0, 0.9, 4.0, 8, precision="mixed"))
+    assert 0 < small < big
+    assert mixed < big  # FP32 phase tables
+
+
+@pytest.mark.parametrize("K", [1, 2, 8, 13, 20, 40])
+def test_kset_size_matches_oracle(K):
+    assert ew.kset_size(K) == len(oracle.kset(K, half=True))
+
+
+def test_plan_without_gpu_reports_device_error():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is visible")
+    except Exception:
+        pass
+    p = ew.make_params(64, 4.0, 1.0, 2.0, 4)
+    h = ctypes.c_void_p()
+    st = ew.library().ewald_plan(ctypes.byref(p), ctypes.byref(h))
+    assert st == ew.ERR_DEVICE and h.value is None

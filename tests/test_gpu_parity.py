@@ -1,0 +1,170 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bars: plain FP64 within 1e-10 relative (energy, force RMS, dE/dq RMS); mixed
+within 1e-6.  Sizes span several tiles, chunks and cells, with ragged tails.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_01135_amd import workloads as wl
+
+from gpu_helpers import compare, rel_err, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp64", "mixed"]
+
+
+def ref(pos, q, L, a, rc, K):
+    return oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST)
+
+
+SMALL_CASES = [
+    # name, n, L, alpha, r_c, K
+    ("single_cell_rc_gt_halfL", 37, 5.0, 1.1, 4.6, 6),   # nc = 1, many images
+    ("two_cells", 200, 6.0, 1.3, 2.9, 7),                 # nc = 2
+    ("odd_ragged", 1001, 10.0, 0.9, 3.2, 9),               # nc = 3, ragged tail
+    ("k_row_boundaries", 777, 9.0, 1.0, 3.0, 16),          # K a multiple of the segment width
+    ("k_17", 513, 8.0, 0.8, 2.6, 17),
+]
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("case", SMALL_CASES, ids=[c[0] for c in SMALL_CASES])
+def test_random_systems(case, precision):
+    name, n, L, a, rc, K = case
+    pos, q = wl.random_neutral(n, L, seed=n)
+    pos = pos + np.array([3.3 * L, -1.7 * L, 0.25])  # positions outside the box
+    compare(run_gpu(pos, q, L, a, rc, K, precision), ref(pos, q, L, a, rc, K), precision, name)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_non_neutral_background(precision):
+    pos, q = wl.random_neutral(300, 7.0, seed=5, neutral=False)
+    assert abs(q.sum()) > 0.3
+    compare(run_gpu(pos, q, 7.0, 1.0, 3.4, 9, precision), ref(pos, q, 7.0, 1.0, 3.4, 9), precision, "bg")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rocksalt8(seed, precision):
+    s = wl.make_config("rocksalt8", seed)
+    compare(run_gpu(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max, precision),
+            ref(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max), precision, f"rocksalt8/{seed}")
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_rocksalt32_full(precision):
+    s = wl.make_config("rocksalt32", 0)
+    compare(run_gpu(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max, precision),
+            ref(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max), precision, "rocksalt32")
+
+
+def test_madelung_on_gpu():
+    for precision, tol in (("fp64", 1e-12), ("mixed", 1e-6)):
+        pos, q, L = wl.perfect_rock_salt(8)
+        e, f, _, st = run_gpu(pos, q, L, 0.9, 7.9, 14, precision)
+        M = 1.7475645946331822
+        assert st == 0
+        assert abs(e[0] / (-256 * M) - 1) < tol, (precision, e)
+        assert np.abs(f).max() < (1e-11 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_structure_factor_matches_oracle(precision):
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    s = wl.make_config("rocksalt8", 4)
+    _, _, _, sk_ref = oracle.recip_space(s.pos, s.q, s.box_L, s.alpha, s.k_max, oracle.FAST, want_sk=True)
+    kref = oracle.kset(s.k_max, half=True)
+    lookup = {tuple(v): i for i, v in enumerate(kref)}
+    with ew.Plan(len(s.q), s.box_L, s.alpha, s.r_c, s.k_max, precision) as p:
+        dev = torch.device("cuda:0")
+        p.energy_forces(torch.tensor(s.pos, device=dev), torch.tensor(s.q, device=dev))
+        kv = p.kset()
+        sk = p.structure_factor()
+    assert len(kv) == len(kref)
+    idx = np.array([lookup[tuple(v)] for v in kv])
+    assert len(set(idx.tolist())) == len(kref)
+    err = np.abs(sk - sk_ref[idx]).max()
+    assert err < (1e-11 if precision == "fp64" else 2e-5 * math.sqrt(len(s.q))), err
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_closed_form_lattice_structure_factor(precision):
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    pos, q, L = wl.perfect_rock_salt(8)
+    with ew.Plan(len(q), L, 0.9, 4.0, 8, precision) as p:
+        dev = torch.device("cuda:0")
+        p.energy_forces(torch.tensor(pos, device=dev), torch.tensor(q, device=dev))
+        kv = p.kset()
+        sk = p.structure_factor()
+    special = np.all(np.mod(kv, 8) == 4, axis=1)
+    expect = np.where(special, 512.0, 0.0)
+    assert np.abs(sk - expect).max() < (1e-10 if precision == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_determinism_and_invariances(precision):
+    s = wl.make_config("rocksalt8", 7)
+    a = run_gpu(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max, precision)
+    b = run_gpu(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max, precision)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    perm = np.random.default_rng(3).permutation(len(s.q))
+    c = run_gpu(s.pos[perm], s.q[perm], s.box_L, s.alpha, s.r_c, s.k_max, precision)
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert abs(c[0][0] - a[0][0]) <= tol * abs(a[0][0])
+    assert rel_err(c[1], a[1][perm]) <= tol
+    d = run_gpu(s.pos + np.array([0.3, -8.0, 17.1]), s.q, s.box_L, s.alpha, s.r_c, s.k_max, precision)
+    assert abs(d[0][0] - a[0][0]) <= (1e-10 if precision == "fp64" else 1e-6) * abs(a[0][0])
+    assert rel_err(d[1], a[1]) <= (1e-9 if precision == "fp64" else 2e-6)
+    # net force vanishes
+    assert np.abs(a[1].sum(axis=0)).max() <= (1e-10 if precision == "fp64" else 1e-5) * np.abs(a[1]).sum() / len(s.q)
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_plan_reuse_with_smaller_n(precision):
+    from paper_1708_01135_amd import ewald as ew
+    with ew.Plan(3000, 9.0, 1.0, 3.0, 10, precision) as p:
+        for n, seed in ((3000, 1), (17, 2), (1, 3), (2048, 4)):
+            pos, q = wl.random_neutral(n, 9.0, seed=seed, neutral=n > 1)
+            got = run_gpu(pos, q, 9.0, 1.0, 3.0, 10, precision, plan=p)
+            exp = ref(pos, q, 9.0, 1.0, 3.0, 10)
+            if n == 1:
+                # a lone charge feels no force (its images are symmetric): only
+                # rounding is left, so check it absolutely
+                assert got[3] == 0
+                assert abs(got[0][0] - exp[0][0]) <= (1e-12 if precision == "fp64" else 1e-6) * abs(exp[0][0])
+                assert np.abs(got[1]).max() <= (1e-14 if precision == "fp64" else 1e-8)
+                continue
+            compare(got, exp, precision, f"reuse n={n}")
+
+
+def test_capacity_and_nonfinite():
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    dev = torch.device("cuda:0")
+    with ew.Plan(100, 6.0, 1.0, 3.0, 6, "fp64") as p:
+        pos = torch.rand((101, 3), dtype=torch.float64, device=dev) * 6
+        q = torch.zeros(101, dtype=torch.float64, device=dev)
+        with pytest.raises(ew.EwaldError) as ei:
+            p.energy_forces(pos, q)
+        assert ei.value.status == ew.ERR_CAPACITY
+        pos = pos[:50].contiguous()
+        q = q[:50].contiguous()
+        q[::2] = 1.0
+        q[1::2] = -1.0
+        pos[7, 1] = float("nan")
+        e, f, _ = p.energy_forces(pos, q)
+        torch.cuda.synchronize()
+        assert math.isnan(e[0].item())
+        assert p.status() == ew.ERR_NONFINITE
+        assert p.status() == ew.OK  # cleared
+        pos[7, 1] = 1.0
+        e, f, _ = p.energy_forces(pos, q)
+        torch.cuda.synchronize()
+        assert math.isfinite(e[0].item()) and p.status() == ew.OK
