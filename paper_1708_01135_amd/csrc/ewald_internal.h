@@ -98,20 +98,21 @@ struct RecipArgs {
 template <typename R>
 hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const d4 *pq, typename Cplx<R>::type *tx,
                         typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
-template <typename R>
-hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, int tile,
-                     const typename Cplx<R>::type *tx, const typename Cplx<R>::type *ty,
-                     const typename Cplx<R>::type *tz, const int *unit_group, const int *unit_seg,
-                     const int *row_nx, const int *row_ny, d4 *part);
+// structure factor (FP64 phases and sums in both precisions)
+size_t sk_smem_bytes(int ts, int K1);
+int sk_tile(int K1);
+hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx, const c64 *ty,
+                     const c64 *tz, const int *unit_group, const int *unit_seg, const int *row_nx, const int *row_ny,
+                     d4 *part);
 template <typename R>
 hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, const d4 *part,
                             const int *unit_group, const int *unit_seg, const int *row_nx,
                             const int *row_ny, const int *row_m, const int *row_item, const double *ck,
                             d4 *sk, R *rec, double *erec_part);
+// gather items carry a packed word: segment << 16 | n_x << 8 | (n_y + 128)
 template <typename R>
 hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split,
-                         const d4 *pq, const typename Cplx<R>::type *tz, const int *item_nx,
-                         const int *item_ny, const int *item_seg, const R *rec, d4 *gpart);
+                         const d4 *pq, const c64 *tz, const int *item_meta, const R *rec, d4 *gpart);
 
 struct PairArgs {
     int64_t n;

@@ -77,100 +77,168 @@ __global__ __launch_bounds__(256) void k_phase(int64_t n, double L, int KP, cons
 }
 
 // --------------------------------------------------------------------- k_sk
-template <typename R>
-__global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_len, int tile, int KP, int K1,
-                                                         const typename Cplx<R>::type *__restrict__ tx,
-                                                         const typename Cplx<R>::type *__restrict__ ty,
-                                                         const typename Cplx<R>::type *__restrict__ tz,
+// Block = kSkWaves waves on one unit (64 rows x one segment); the block's
+// particle chunk is cut into tiles of `ts` particles and wave w takes tiles
+// w, w + kSkWaves, ...  Each wave stages the x/y power tables of its own tile
+// in a private, double-buffered LDS area (the next tile's global loads are in
+// flight while the current tile is consumed), so no block barrier is needed
+// until the final fixed-order reduction over the waves.  The z powers of the
+// unit's segment are wave-uniform and come through the scalar path, prefetched
+// one particle ahead; so are the lane's x/y entries.
+constexpr int kSkStage = 4;  // staged table entries per lane and tile (upper bound)
+
+// Operands of one particle for k_sk: the segment's kQ z powers (wave-uniform,
+// scalar path) and the lane's x/y powers from the staged tile (LDS).
+__device__ inline void load_ops(const c64 *__restrict__ zrow, const c64 *cur, int jj, int KP, int K1, int nx, int ay,
+                                c64 (&z)[kQ], c64 &a, c64 &b)
+{
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) z[k] = zrow[(size_t)jj * KP + k];
+    a = cur[jj * 2 * K1 + nx];
+    b = cur[jj * 2 * K1 + ay];
+}
+
+// Scalar and LDS loads share one wait counter and scalar loads return out of
+// order; this empty statement makes the prefetched operands due at this point
+// (after the preceding FMAs) instead of letting the compiler sink the loads
+// next to their use.  It contains no instructions.
+__device__ inline void pin_ops(const c64 (&z)[kQ], const c64 &a, const c64 &b)
+{
+    asm volatile("" ::"s"(z[0].re), "s"(z[0].im), "s"(z[1].re), "s"(z[1].im), "s"(z[2].re), "s"(z[2].im),
+                 "s"(z[3].re), "s"(z[3].im), "s"(z[4].re), "s"(z[4].im), "s"(z[5].re), "s"(z[5].im), "s"(z[6].re),
+                 "s"(z[6].im), "s"(z[7].re), "s"(z[7].im), "v"(a.re), "v"(a.im), "v"(b.re), "v"(b.im));
+}
+
+// W = (q x-power)(y-power or its conjugate); accumulate the four real products
+// that give both S(+a) and S(-a) for the kQ values of a in the segment.
+__device__ inline void sk_fma(const c64 (&z)[kQ], const c64 &a, const c64 &b, double ysign, double (&A)[kQ],
+                              double (&B)[kQ], double (&Cc)[kQ], double (&D)[kQ])
+{
+    const double bi = b.im * ysign;
+    const double wr = a.re * b.re - a.im * bi;
+    const double wi = a.re * bi + a.im * b.re;
+#pragma unroll
+    for (int k = 0; k < kQ; ++k) {
+        A[k] = fma(wr, z[k].re, A[k]);
+        B[k] = fma(wi, z[k].im, B[k]);
+        Cc[k] = fma(wr, z[k].im, Cc[k]);
+        D[k] = fma(wi, z[k].re, D[k]);
+    }
+}
+
+
+__global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_len, int ts, int KP, int K1,
+                                                         const c64 *__restrict__ tx, const c64 *__restrict__ ty,
+                                                         const c64 *__restrict__ tz,
                                                          const int *__restrict__ unit_group,
                                                          const int *__restrict__ unit_seg,
                                                          const int *__restrict__ row_nx,
                                                          const int *__restrict__ row_ny, int n_rows, int n_units,
                                                          d4 *__restrict__ part)
 {
-    using C = typename Cplx<R>::type;
     extern __shared__ __align__(32) unsigned char smem[];
-    C *lx = reinterpret_cast<C *>(smem);
-    C *ly = lx + (size_t)tile * K1;
-    d4 *red = reinterpret_cast<d4 *>(smem);
-
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
+    const int per_tile = ts * 2 * K1;                                   // c64 entries in one tile
+    c64 *buf = reinterpret_cast<c64 *>(smem) + (size_t)wave * 2 * per_tile;  // two buffers
+    d4 *red = reinterpret_cast<d4 *>(smem);
+
     const int u = blockIdx.x;
-    const int g = unit_group[u];
     const int seg = unit_seg[u];
-    const int r = g * kLanes + lane;
+    const int r = unit_group[u] * kLanes + lane;
     int nx = 0, ny = 0;
     if (r < n_rows) {
         nx = row_nx[r];
         ny = row_ny[r];
     }
-    const int ay = ny < 0 ? -ny : ny;
-    const R ysign = ny < 0 ? R(-1) : R(1);
+    const int ay = K1 + (ny < 0 ? -ny : ny);  // y entries follow the x entries of a particle
+    const double ysign = ny < 0 ? -1.0 : 1.0;
     const int64_t j0 = (int64_t)blockIdx.y * chunk_len;
     const int64_t j1 = (j0 + chunk_len < n) ? j0 + chunk_len : n;
+    const int n_tiles = j1 > j0 ? (int)((j1 - j0 + ts - 1) / ts) : 0;
 
-    R A[kQ], B[kQ], Cc[kQ], D[kQ];
-    double Pr[kQ], Pi[kQ], Mr[kQ], Mi[kQ];
+    double A[kQ], B[kQ], Cc[kQ], D[kQ];
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-        A[k] = B[k] = Cc[k] = D[k] = R(0);
-        Pr[k] = Pi[k] = Mr[k] = Mi[k] = 0.0;
-    }
+    for (int k = 0; k < kQ; ++k) A[k] = B[k] = Cc[k] = D[k] = 0.0;
 
-    for (int64_t t0 = j0; t0 < j1; t0 += tile) {
-        const int tn = (int)((j1 - t0) < tile ? (j1 - t0) : tile);
-        __syncthreads();
-        for (int e = threadIdx.x; e < tn * K1; e += kSkWaves * kLanes) {
-            const int jj = e / K1;
-            const int m = e - jj * K1;
-            lx[e] = tx[(t0 + jj) * KP + m];
-            ly[e] = ty[(t0 + jj) * KP + m];
-        }
-        __syncthreads();
-        for (int jj = wave; jj < tn; jj += kSkWaves) {
-            const C a = lx[jj * K1 + nx];
-            const C b = ly[jj * K1 + ay];
-            const R bi = b.im * ysign;
-            const R wr = a.re * b.re - a.im * bi;
-            const R wi = a.re * bi + a.im * b.re;
-            const C *zp = tz + (t0 + jj) * KP + seg * kQ;  // wave-uniform address
+    // Staging of one tile: entry e = lane + 64 k (k < kSkStage) is particle
+    // e / (2 K1), table x or y, power e % K1; offsets are fixed per lane.
+    static_assert(kSkStage == 4, "staging uses four named registers");
+    int off[kSkStage];
+    bool isy[kSkStage];
 #pragma unroll
-            for (int k = 0; k < kQ; ++k) {
-                const C z = zp[k];
-                A[k] = fma(wr, z.re, A[k]);
-                B[k] = fma(wi, z.im, B[k]);
-                Cc[k] = fma(wr, z.im, Cc[k]);
-                D[k] = fma(wi, z.re, D[k]);
-            }
+    for (int k = 0; k < kSkStage; ++k) {
+        const int e = lane + k * kLanes;
+        const int jj = e / (2 * K1), rem = e - jj * 2 * K1;
+        isy[k] = rem >= K1;
+        off[k] = jj * KP + (isy[k] ? rem - K1 : rem);
+    }
+    c64 st0, st1, st2, st3;
+    auto ld = [&](int64_t tb, int cnt, int k) -> c64 {
+        const int e = lane + k * kLanes;
+        const int o = e < cnt ? off[k] : 0;  // clamp to the tile's first entry
+        return (isy[k] && e < cnt ? ty : tx)[tb * KP + o];
+    };
+    auto fetch = [&](int t) {
+        const int64_t tb = j0 + (int64_t)t * ts;
+        const int cnt = (int)((j1 - tb) < ts ? (j1 - tb) : ts) * 2 * K1;
+        st0 = ld(tb, cnt, 0);
+        st1 = ld(tb, cnt, 1);
+        st2 = ld(tb, cnt, 2);
+        st3 = ld(tb, cnt, 3);
+    };
+    auto store = [&](int t, int slot) {
+        const int64_t tb = j0 + (int64_t)t * ts;
+        const int cnt = (int)((j1 - tb) < ts ? (j1 - tb) : ts) * 2 * K1;
+        c64 *dst = buf + slot * per_tile;
+        if (lane < cnt) dst[lane] = st0;
+        if (lane + kLanes < cnt) dst[lane + kLanes] = st1;
+        if (lane + 2 * kLanes < cnt) dst[lane + 2 * kLanes] = st2;
+        if (lane + 3 * kLanes < cnt) dst[lane + 3 * kLanes] = st3;
+    };
+
+    int t = wave;
+    if (t < n_tiles) {
+        fetch(t);
+        store(t, 0);
+    }
+    int slot = 0;
+    for (; t < n_tiles; t += kSkWaves) {
+        const int tn_next = t + kSkWaves;
+        if (tn_next < n_tiles) fetch(tn_next);  // in flight during this tile
+        __builtin_amdgcn_wave_barrier();
+        const int64_t tb = j0 + (int64_t)t * ts;
+        const int tn = (int)((j1 - tb) < ts ? (j1 - tb) : ts);
+        const c64 *cur = buf + slot * per_tile;
+        const c64 *zrow = tz + tb * KP + seg * kQ;
+        // two alternating operand sets: the loads of one particle are issued
+        // before the FMAs of the previous one and are made due after them
+        c64 z0[kQ], z1[kQ], a0, b0, a1, b1;
+        load_ops(zrow, cur, 0, KP, K1, nx, ay, z0, a0, b0);
+        for (int jj = 0; jj < tn; jj += 2) {
+            const int j1n = jj + 1 < tn ? jj + 1 : tn - 1;
+            load_ops(zrow, cur, j1n, KP, K1, nx, ay, z1, a1, b1);
+            sk_fma(z0, a0, b0, ysign, A, B, Cc, D);
+            pin_ops(z1, a1, b1);
+            const int j2n = jj + 2 < tn ? jj + 2 : tn - 1;
+            load_ops(zrow, cur, j2n, KP, K1, nx, ay, z0, a0, b0);
+            if (jj + 1 < tn) sk_fma(z1, a1, b1, ysign, A, B, Cc, D);
+            pin_ops(z0, a0, b0);
         }
-        if constexpr (sizeof(R) == 4) {
-            // fold the FP32 partial (<= tile / kSkWaves particles) into FP64
-#pragma unroll
-            for (int k = 0; k < kQ; ++k) {
-                Pr[k] += (double)A[k] - (double)B[k];
-                Pi[k] += (double)Cc[k] + (double)D[k];
-                Mr[k] += (double)A[k] + (double)B[k];
-                Mi[k] += (double)D[k] - (double)Cc[k];
-                A[k] = B[k] = Cc[k] = D[k] = R(0);
-            }
+        if (tn_next < n_tiles) {
+            slot ^= 1;
+            __builtin_amdgcn_wave_barrier();
+            store(tn_next, slot);
         }
     }
+    // S(+a) = sum W z = (A - B, C + D);  S(-a) = sum W conj(z) = (A + B, D - C)
     d4 mine[kQ];
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
-        if constexpr (sizeof(R) == 4) {
-            mine[k].a = Pr[k];
-            mine[k].b = Pi[k];
-            mine[k].c = Mr[k];
-            mine[k].d = Mi[k];
-        } else {
-            // S(+a) = sum W z = (A - B, C + D);  S(-a) = sum W conj(z) = (A + B, D - C)
-            mine[k].a = (double)A[k] - (double)B[k];
-            mine[k].b = (double)Cc[k] + (double)D[k];
-            mine[k].c = (double)A[k] + (double)B[k];
-            mine[k].d = (double)D[k] - (double)Cc[k];
-        }
+        mine[k].a = A[k] - B[k];
+        mine[k].b = Cc[k] + D[k];
+        mine[k].c = A[k] + B[k];
+        mine[k].d = D[k] - Cc[k];
     }
     // fixed-order sum over the block's waves through LDS (aliases the tiles)
     for (int w = 1; w < kSkWaves; ++w) {
@@ -276,12 +344,49 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
 }
 
 // ----------------------------------------------------------------- k_gather
+// Lanes own particles; the loop over (segment, row) items is wave-uniform.  An
+// item's coefficients (kQ values of a, 8 each) are consumed in four quarters of
+// two a values; quarters alternate between two scalar register sets so that the
+// loads of one quarter are in flight during the FMAs of the previous one.  The
+// next item's packed (segment, n_x, n_y) word travels with its first quarter.
+template <typename R>
+__device__ inline void load_quarter(const R *__restrict__ rec, int g, R (&v)[16])
+{
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = rec[(size_t)g * 16 + k];
+}
+
+template <typename R>
+__device__ inline void pin_quarter(const R (&v)[16], int meta)
+{
+    asm volatile("" ::"s"(v[0]), "s"(v[1]), "s"(v[2]), "s"(v[3]), "s"(v[4]), "s"(v[5]), "s"(v[6]), "s"(v[7]),
+                 "s"(v[8]), "s"(v[9]), "s"(v[10]), "s"(v[11]), "s"(v[12]), "s"(v[13]), "s"(v[14]), "s"(v[15]),
+                 "s"(meta));
+}
+
+// T += sum over the quarter's two a values of the 8 coefficient products.
+template <typename R>
+__device__ inline void gather_fma(const R (&v)[16], const typename Cplx<R>::type *p, R &Tr, R &Ti, R &Zr, R &Zi)
+{
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const R pr = p[h].re, pi = p[h].im;
+        const R *c = v + 8 * h;
+        Tr = fma(c[0], pr, Tr);
+        Tr = fma(c[1], pi, Tr);
+        Ti = fma(c[2], pi, Ti);
+        Ti = fma(c[3], pr, Ti);
+        Zr = fma(c[4], pr, Zr);
+        Zr = fma(c[5], pi, Zr);
+        Zi = fma(c[6], pi, Zi);
+        Zi = fma(c[7], pr, Zi);
+    }
+}
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, SplitTable split,
-                                                const d4 *__restrict__ pq,
-                                                const typename Cplx<R>::type *__restrict__ tz,
-                                                const int *__restrict__ item_nx, const int *__restrict__ item_ny,
-                                                const int *__restrict__ item_seg, const R *__restrict__ rec,
+                                                const d4 *__restrict__ pq, const c64 *__restrict__ tz,
+                                                const int *__restrict__ item_meta, const R *__restrict__ rec,
                                                 d4 *__restrict__ gpart)
 {
     using C = typename Cplx<R>::type;
@@ -300,12 +405,18 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, Spl
     for (int k = 0; k < kQ; ++k) p[k] = make_c<R>(0.0, 0.0);
     int cur_seg = -1, pnx = -1000000, pny = 0;
     double wr64 = 1.0, wi64 = 0.0;
+    R qa[16], qb[16];
+    int meta = 0;
+    if (i0 < i1) {
+        load_quarter(rec, 4 * i0, qa);
+        meta = item_meta[i0];
+    }
     for (int it = i0; it < i1; ++it) {
-        const int nx = item_nx[it], ny = item_ny[it], s = item_seg[it];
+        const int s = meta >> 16, nx = (meta >> 8) & 0xff, ny = (meta & 0xff) - 128;
         if (s != cur_seg) {
-            const C *src = tz + jj * KP + s * kQ;
+            const c64 *src = tz + jj * KP + s * kQ;
 #pragma unroll
-            for (int k = 0; k < kQ; ++k) p[k] = src[k];
+            for (int k = 0; k < kQ; ++k) p[k] = make_c<R>(src[k].re, src[k].im);
             cur_seg = s;
             pnx = -1000000;
         }
@@ -318,21 +429,24 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, Spl
         }
         pnx = nx;
         pny = ny;
-        const R wr = (R)wr64, wi = (R)wi64;
-        const R *rr = rec + (size_t)it * kQ * 8;  // wave-uniform
         R Tr = 0, Ti = 0, Zr = 0, Zi = 0;
-#pragma unroll
-        for (int k = 0; k < kQ; ++k) {
-            const R pr = p[k].re, pi = p[k].im;
-            Tr = fma(rr[8 * k + 0], pr, Tr);
-            Tr = fma(rr[8 * k + 1], pi, Tr);
-            Ti = fma(rr[8 * k + 2], pi, Ti);
-            Ti = fma(rr[8 * k + 3], pr, Ti);
-            Zr = fma(rr[8 * k + 4], pr, Zr);
-            Zr = fma(rr[8 * k + 5], pi, Zr);
-            Zi = fma(rr[8 * k + 6], pi, Zi);
-            Zi = fma(rr[8 * k + 7], pr, Zi);
-        }
+        const int g = 4 * it;
+        load_quarter(rec, g + 1, qb);
+        gather_fma(qa, p + 0, Tr, Ti, Zr, Zi);
+        pin_quarter(qb, 0);
+        load_quarter(rec, g + 2, qa);
+        gather_fma(qb, p + 2, Tr, Ti, Zr, Zi);
+        pin_quarter(qa, 0);
+        load_quarter(rec, g + 3, qb);
+        gather_fma(qa, p + 4, Tr, Ti, Zr, Zi);
+        pin_quarter(qb, 0);
+        const int itn = it + 1 < i1 ? it + 1 : it;  // next item (clamped)
+        load_quarter(rec, 4 * itn, qa);
+        const int meta_n = item_meta[itn];
+        gather_fma(qb, p + 6, Tr, Ti, Zr, Zi);
+        pin_quarter(qa, meta_n);
+        meta = meta_n;
+        const R wr = (R)wr64, wi = (R)wi64;
         const R re = wr * Tr - wi * Ti;   // Re(w T)
         const R im = wr * Ti + wi * Tr;   // Im(w T)
         const R imz = wr * Zi + wi * Zr;  // Im(w Tz)
@@ -362,24 +476,33 @@ hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const d4 *pq, typenam
     return hipGetLastError();
 }
 
-template <typename R>
-size_t sk_smem_bytes(int tile, int K1)
+// LDS bytes of one structure-factor block: two staged tiles per wave, or the
+// 16 KB cross-wave reduction buffer, whichever is larger.
+size_t sk_smem_bytes(int ts, int K1)
 {
-    const size_t tab = 2 * (size_t)tile * K1 * sizeof(typename Cplx<R>::type);
+    const size_t tab = (size_t)kSkWaves * 2 * ts * 2 * K1 * sizeof(c64);
     const size_t red = (size_t)kQ * kLanes * sizeof(d4);
     return tab > red ? tab : red;
 }
 
-template <typename R>
-hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, int tile,
-                     const typename Cplx<R>::type *tx, const typename Cplx<R>::type *ty,
-                     const typename Cplx<R>::type *tz, const int *unit_group, const int *unit_seg,
-                     const int *row_nx, const int *row_ny, d4 *part)
+// Particles per staged tile: the largest ts <= 8 whose 2*ts*K1 entries fit the
+// per-lane staging registers (kSkStage per lane).
+int sk_tile(int K1)
+{
+    int ts = kSkStage * kLanes / (2 * K1);
+    if (ts > 8) ts = 8;
+    return ts < 1 ? 1 : ts;
+}
+
+hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx, const c64 *ty,
+                     const c64 *tz, const int *unit_group, const int *unit_seg, const int *row_nx, const int *row_ny,
+                     d4 *part)
 {
     const int K1 = a.K + 1;
-    hipLaunchKernelGGL(k_sk<R>, dim3(a.n_units, n_chunks), dim3(kSkWaves * kLanes), sk_smem_bytes<R>(tile, K1), s,
-                       a.n, chunk_len, tile, a.KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, a.n_rows,
-                       a.n_units, part);
+    const int ts = sk_tile(K1);
+    hipLaunchKernelGGL(k_sk, dim3(a.n_units, n_chunks), dim3(kSkWaves * kLanes), sk_smem_bytes(ts, K1), s, a.n,
+                       chunk_len, ts, a.KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, a.n_rows, a.n_units,
+                       part);
     return hipGetLastError();
 }
 
@@ -396,27 +519,21 @@ hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, con
 
 template <typename R>
 hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, const d4 *pq,
-                         const typename Cplx<R>::type *tz, const int *item_nx, const int *item_ny,
-                         const int *item_seg, const R *rec, d4 *gpart)
+                         const c64 *tz, const int *item_meta, const R *rec, d4 *gpart)
 {
     hipLaunchKernelGGL(k_gather<R>, dim3(ceil_div(a.n, 256), n_split), dim3(256), 0, s, a.n, a.L, a.KP, split, pq,
-                       tz, item_nx, item_ny, item_seg, rec, gpart);
+                       tz, item_meta, rec, gpart);
     return hipGetLastError();
 }
 
 #define EWK_INSTANTIATE(R)                                                                                         \
     template hipError_t launch_phase<R>(hipStream_t, const RecipArgs &, const d4 *, Cplx<R>::type *,             \
                                         Cplx<R>::type *, Cplx<R>::type *);                                         \
-    template size_t sk_smem_bytes<R>(int, int);                                                                    \
-    template hipError_t launch_sk<R>(hipStream_t, const RecipArgs &, int, int, int, const Cplx<R>::type *,         \
-                                     const Cplx<R>::type *, const Cplx<R>::type *, const int *, const int *,      \
-                                     const int *, const int *, d4 *);                                              \
     template hipError_t launch_sk_reduce<R>(hipStream_t, const RecipArgs &, int, const d4 *, const int *,          \
                                             const int *, const int *, const int *, const int *, const int *,      \
                                             const double *, d4 *, R *, double *);                                  \
     template hipError_t launch_gather<R>(hipStream_t, const RecipArgs &, int, const SplitTable &, const d4 *,      \
-                                         const Cplx<R>::type *, const int *, const int *, const int *, const R *, \
-                                         d4 *);
+                                         const c64 *, const int *, const R *, d4 *);
 
 EWK_INSTANTIATE(float)
 EWK_INSTANTIATE(double)

@@ -14,8 +14,6 @@ using namespace ewk;
 namespace ewk {
 const char *const kKernelClassNames[KC_COUNT] = {"bin",    "scan",   "scatter",  "cellsort", "phase",  "sk",
                                                  "sk_reduce", "gather", "pair_list", "pair", "final_p", "final_e"};
-template <typename R>
-size_t sk_smem_bytes(int tile, int K1);
 int bin_blocks(int64_t n);
 }  // namespace ewk
 
@@ -38,7 +36,8 @@ struct KLayout {
     std::vector<int> unit_g, unit_s;
     // gather items: per segment, rows with m >= kQ*s in (nx, ny) order
     std::vector<int> item_nx, item_ny, item_seg;
-    std::vector<int> row_item;  // [seg * n_rows + row] -> item, or -1
+    std::vector<int> item_meta;  // seg << 16 | nx << 8 | (ny + 128)
+    std::vector<int> row_item;   // [seg * n_rows + row] -> item, or -1
 };
 
 int isqrt_floor(int v)
@@ -107,6 +106,9 @@ void build_klayout(int K, KLayout &kl)
             kl.item_seg.push_back(s);
         }
     kl.n_items = (int)kl.item_nx.size();
+    kl.item_meta.resize(kl.n_items);
+    for (int i = 0; i < kl.n_items; ++i)
+        kl.item_meta[i] = (kl.item_seg[i] << 16) | (kl.item_nx[i] << 8) | (kl.item_ny[i] + 128);
 }
 
 int cells_per_axis(double L, double rc)
@@ -118,18 +120,10 @@ int cells_per_axis(double L, double rc)
     return nc;
 }
 
-int choose_tile(bool mixed, int K1)
-{
-    for (int t = 64; t >= kSkWaves; t /= 2) {
-        const size_t b = mixed ? sk_smem_bytes<float>(t, K1) : sk_smem_bytes<double>(t, K1);
-        if (b <= kSkSmemBudget) return t;
-    }
-    return kSkWaves;
-}
-
 int sk_chunks(int64_t n, int n_units, int tile)
 {
-    const int64_t by_work = (n + tile - 1) / tile;  // at least one tile per chunk
+    // at least one tile per wave of a block
+    const int64_t by_work = (n + (int64_t)tile * kSkWaves - 1) / ((int64_t)tile * kSkWaves);
     int64_t want = (kSkTargetBlocks + n_units - 1) / n_units;
     if (want < 1) want = 1;
     int64_t c = std::min<int64_t>(by_work, want);
@@ -175,9 +169,9 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     const bool mixed = p.precision == EWALD_PRECISION_MIXED;
     const int64_t N = p.n_max;
     const size_t ncell = (size_t)nc * nc * nc;
-    const size_t creal = mixed ? sizeof(c32) : sizeof(c64);
+    const size_t creal = sizeof(c64);  // phase tables are FP64 in both precisions
     const size_t real = mixed ? sizeof(float) : sizeof(double);
-    const int tile = choose_tile(mixed, kl.K + 1);
+    const int tile = sk_tile(kl.K + 1);
     z.max_chunks = sk_chunks(N, kl.n_units, tile);
     const size_t n_slots = (size_t)kl.n_units * kQ * kLanes;
     const size_t gcap = std::min<size_t>((size_t)kMaxSplit * N, (size_t)kGatherTargetBlocks * 256 + N);
@@ -394,7 +388,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->nc = cells_per_axis(params->box_L, params->r_c);
     p->ncell = p->nc * p->nc * p->nc;
     build_klayout(params->k_max, p->kl);
-    p->tile = choose_tile(p->mixed, params->k_max + 1);
+    p->tile = sk_tile(params->k_max + 1);
     compute_sizes(*params, p->kl, p->nc, p->sz);
 
     int ndev = 0;
@@ -470,7 +464,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (e == hipSuccess) e = upload(p->row_item, kl.row_item, s);
     if (e == hipSuccess) e = upload(p->item_nx, kl.item_nx, s);
     if (e == hipSuccess) e = upload(p->item_ny, kl.item_ny, s);
-    if (e == hipSuccess) e = upload(p->item_seg, kl.item_seg, s);
+    if (e == hipSuccess) e = upload(p->item_seg, kl.item_meta, s);
     // counters start at zero; afterwards every evaluation leaves them cleared
     if (e == hipSuccess) e = hipMemsetAsync(p->counts, 0, z.counts, s);
     if (e == hipSuccess) e = hipMemsetAsync(p->fill, 0, z.fill, s);
@@ -527,38 +521,38 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
     });
     run(KC_SCATTER, [&] { return launch_scatter(s, ca, p->cell_of, p->cell_start, p->fill, p->tmp_idx); });
     run(KC_CELLSORT, [&] { return launch_cellsort(s, ca, p->cell_start, p->tmp_idx, pos, q, p->perm, p->pq); });
-    if (p->mixed) {
-        auto *tx = static_cast<c32 *>(p->tx), *ty = static_cast<c32 *>(p->ty), *tz = static_cast<c32 *>(p->tz);
-        run(KC_PHASE, [&] { return launch_phase<float>(s, ra, p->pq, tx, ty, tz); });
-        run(KC_SK, [&] {
-            return launch_sk<float>(s, ra, n_chunks, chunk_len, p->tile, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx,
-                                    p->row_ny, p->part);
-        });
-        run(KC_SKREDUCE, [&] {
-            return launch_sk_reduce<float>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
-                                           p->row_m, p->row_item, p->ck, p->sk, static_cast<float *>(p->rec),
-                                           p->erec);
-        });
-        run(KC_GATHER, [&] {
-            return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_nx, p->item_ny, p->item_seg,
-                                        static_cast<const float *>(p->rec), p->gpart);
-        });
-    } else {
+    // Phase tables and the structure factor are FP64 in both precisions (FP32
+    // phase rounding leaves ~1e-5 relative error in S_k of near-lattice systems
+    // at small k); the mixed path rounds phases and coefficients to FP32 in the
+    // gather and evaluates the pair functions in FP32.
+    {
         auto *tx = static_cast<c64 *>(p->tx), *ty = static_cast<c64 *>(p->ty), *tz = static_cast<c64 *>(p->tz);
         run(KC_PHASE, [&] { return launch_phase<double>(s, ra, p->pq, tx, ty, tz); });
         run(KC_SK, [&] {
-            return launch_sk<double>(s, ra, n_chunks, chunk_len, p->tile, tx, ty, tz, p->unit_g, p->unit_s,
-                                     p->row_nx, p->row_ny, p->part);
+            return launch_sk(s, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
+                             p->part);
         });
-        run(KC_SKREDUCE, [&] {
-            return launch_sk_reduce<double>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
-                                            p->row_m, p->row_item, p->ck, p->sk, static_cast<double *>(p->rec),
-                                            p->erec);
-        });
-        run(KC_GATHER, [&] {
-            return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_nx, p->item_ny, p->item_seg,
-                                         static_cast<const double *>(p->rec), p->gpart);
-        });
+        if (p->mixed) {
+            run(KC_SKREDUCE, [&] {
+                return launch_sk_reduce<float>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
+                                               p->row_ny, p->row_m, p->row_item, p->ck, p->sk,
+                                               static_cast<float *>(p->rec), p->erec);
+            });
+            run(KC_GATHER, [&] {
+                return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_seg,
+                                            static_cast<const float *>(p->rec), p->gpart);
+            });
+        } else {
+            run(KC_SKREDUCE, [&] {
+                return launch_sk_reduce<double>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
+                                                p->row_ny, p->row_m, p->row_item, p->ck, p->sk,
+                                                static_cast<double *>(p->rec), p->erec);
+            });
+            run(KC_GATHER, [&] {
+                return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_seg,
+                                             static_cast<const double *>(p->rec), p->gpart);
+            });
+        }
     }
     const int max_pitems = p->ncell + ceil_div(n, kPairHome);
     run(KC_PAIRLIST, [&] {
