@@ -62,14 +62,16 @@ typedef enum {
 /* Arithmetic of the hot kernels. */
 enum {
     EWALD_PRECISION_FP64 = 0,  /* every step in IEEE double                          */
-    EWALD_PRECISION_MIXED = 1  /* FP32 phases, pair functions and products; FP64
-                                  displacements, angles, S(k) accumulation across
-                                  particles, per-particle sums and all energies   */
+    EWALD_PRECISION_MIXED = 1  /* FP32 pair functions (rsqrt, erfc, exp) and FP32
+                                  phases, coefficients and products in the force
+                                  gather; FP64 displacements, phase generation,
+                                  the structure factor, per-particle sums and all
+                                  energies                                         */
 };
 
 /* Plan parameters.
- *   n_max      largest N the plan will be called with (>= 1); all workspace is
- *              sized for it at plan time.
+ *   n_max      largest N the plan will be called with, 1 <= n_max <= 2^25; all
+ *              workspace is sized for it at plan time.
  *   box_L      side of the periodic cube (> 0).
  *   alpha      Gaussian splitting exponent (> 0), see above.
  *   r_c        real-space cutoff, 0 < r_c <= box_L; the test is |d|^2 < r_c^2.
@@ -109,7 +111,7 @@ size_t ewald_plan_workspace_bytes(const ewald_params *params);
 int64_t ewald_kset_size(int32_t k_max);
 
 /* Create a plan: validates *params, builds the k-set tables and the cell grid
- * (n_c = floor(L / r_c) cells per axis) and allocates all device workspace for
+ * (n_c = floor(2 L / r_c) cells per axis) and allocates all device workspace for
  * n_max.  On success *out receives the plan; on failure *out is set to NULL and
  * nothing stays allocated.  Errors: INVALID_ARG (bad params or out == NULL),
  * OUT_OF_MEMORY, DEVICE. */

@@ -98,6 +98,8 @@ struct RecipArgs {
 template <typename R>
 hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const d4 *pq, typename Cplx<R>::type *tx,
                         typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
+// lanes per slot in the structure-factor reduction (k_sk_reduce)
+constexpr int kRedSlotLanes = 16;
 // structure factor (FP64 phases and sums in both precisions)
 size_t sk_smem_bytes(int ts, int K1);
 int sk_tile(int K1);
@@ -122,18 +124,20 @@ struct PairArgs {
     double rc2;
     double alpha;
 };
-// Real-space neighbour lists: entries are 16-bit (neighbour offset code << 11 |
-// index inside that neighbour cell), list of particle i at list[i * cap ...].
-// Pair work items are (cell, kPairHome consecutive home particles).
+// Real-space cells have side >= r_c / kPairReach, so the stencil spans
+// (2 kPairReach + 1)^3 cells.  Neighbour lists hold 32-bit entries: the sorted
+// index j in the low kPairIndexBits bits and the image-shift code above them;
+// particle i's list is list[i * cap ...].  List-building work items are (cell,
+// kPairHome consecutive home particles).
+constexpr int kPairReach = 2;
 constexpr int kPairHome = 8;
-constexpr int kPairLocalBits = 11;
-constexpr int kPairMaxCell = 1 << kPairLocalBits;  // cells up to 2048 particles use lists
+constexpr int kPairIndexBits = 25;
+constexpr int64_t kPairMaxN = (int64_t)1 << kPairIndexBits;  // largest n_max the lists can index
 hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, const int *n_items,
                             const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
-                            uint16_t *list, int *list_cnt, int cap);
-hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, int max_items, const int *n_items,
-                       const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
-                       const uint16_t *list, const int *list_cnt, int cap, d4 *freal);
+                            uint32_t *list, int *list_cnt, int cap);
+hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *cell_start, const d4 *pq,
+                       const uint32_t *list, const int *list_cnt, int cap, d4 *freal);
 
 struct FinalArgs {
     int64_t n;

@@ -5,22 +5,23 @@
 //
 // Every ordered pair is visited from its i side and forces are written to i
 // alone (as in the paper's pair kernel), so there are no write conflicts and no
-// atomics.  Cells have side h = L/nc >= r_c; the 27 neighbours of a cell are
-// taken as unwrapped offsets, each naming one (cell, image shift) pair, which
-// stays exact for nc = 1 or 2 where one cell appears under several shifts.
+// atomics.  Cells have side h = L/nc >= r_c/2, so every image within r_c lies in
+// the 5^3 cells around a particle's own; the neighbours are taken as unwrapped
+// offsets, each naming one (cell, image shift) pair, which stays exact for small
+// nc where one cell appears under several shifts.
 //
 // Work item = up to kPairHome (8) home particles of one cell; two passes:
-//  1. k_pair_list: lanes hold 64 candidates at a time (one z-column of three
+//  1. k_pair_list: lanes hold 64 candidates at a time (one z-column of five
 //     neighbour cells, read coalesced), the 8 home particles are wave-uniform.
 //     For each home particle the in-range lanes are compacted with a ballot and
 //     appended, in lane order, to that particle's list of 16-bit entries
-//     (neighbour offset code << 11 | index inside that neighbour cell).
+//     (neighbour offset code << 9 | index inside that neighbour cell).
 //  2. k_pair: 8 lanes per home particle walk its list (lane s takes entries
 //     s, s+8, ...), so erfc/exp run only for pairs inside r_c; the 8 partial
 //     sums are combined by a fixed xor-shuffle tree.
 // Both passes run in a fixed order, so results are bitwise reproducible.  A home
 // particle whose list would overflow, or whose neighbourhood holds a cell of
-// more than 2048 particles, is evaluated by the exact direct loop instead.
+// more than 512 particles, is evaluated by the exact direct loop instead.
 //
 // Precision: FP64 computes everything in double.  MIXED forms d and |d|^2 in
 // FP64 (exact cutoff test, no cancellation), evaluates erfc/exp/rsqrt in FP32,
@@ -78,26 +79,46 @@ __device__ inline void pair_term(double dx, double dy, double dz, double r2, dou
     }
 }
 
-// Neighbour o = (ox+1)*9 + (oy+1)*3 + (oz+1) of cell (cx, cy, cz): wrapped cell
-// id and the image shift s that is added to the neighbour's positions.
+constexpr int kSpan = 2 * kPairReach + 1;              // cells per axis in the stencil
+constexpr int kStencil = kSpan * kSpan * kSpan;          // neighbour offsets
+constexpr int kCenter = (kStencil - 1) / 2;              // the home cell itself (zero shift)
+
+// Neighbour o = ((ox+R)*kSpan + (oy+R))*kSpan + (oz+R) of cell (cx, cy, cz), R =
+// kPairReach: wrapped cell id and the image shift s added to its positions.
+__device__ inline int wrap_axis(int v, int nc, double L, double &sh)
+{
+    int w = v >= 0 ? v / nc : -((-v + nc - 1) / nc);  // floor(v / nc)
+    sh = (double)w * L;
+    return v - w * nc;
+}
+
 __device__ inline int neighbour(int nc, double L, int cx, int cy, int cz, int o, double &sx, double &sy,
                                 double &sz)
 {
-    int vx = cx + o / 9 - 1, vy = cy + (o / 3) % 3 - 1, vz = cz + o % 3 - 1;
-    sx = sy = sz = 0.0;
-    if (vx < 0) { vx += nc; sx = -L; } else if (vx >= nc) { vx -= nc; sx = L; }
-    if (vy < 0) { vy += nc; sy = -L; } else if (vy >= nc) { vy -= nc; sy = L; }
-    if (vz < 0) { vz += nc; sz = -L; } else if (vz >= nc) { vz -= nc; sz = L; }
+    const int vx = wrap_axis(cx + o / (kSpan * kSpan) - kPairReach, nc, L, sx);
+    const int vy = wrap_axis(cy + (o / kSpan) % kSpan - kPairReach, nc, L, sy);
+    const int vz = wrap_axis(cz + o % kSpan - kPairReach, nc, L, sz);
     return (vx * nc + vy) * nc + vz;
 }
 
-constexpr int kCenter = 13;  // offset code of the home cell itself (zero shift)
+
+// image-shift code of a stencil offset: base-kSpan digits of the per-axis shift
+// multiples (each in [-kPairReach, kPairReach]) -- shift = (code digits - R) * L
+__device__ inline int shift_code(double sx, double sy, double sz, double L)
+{
+    const int ix = (int)rint(sx / L) + kPairReach, iy = (int)rint(sy / L) + kPairReach;
+    const int iz = (int)rint(sz / L) + kPairReach;
+    return (ix * kSpan + iy) * kSpan + iz;
+}
 
 __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, const int *__restrict__ n_items,
                                                   const int *__restrict__ item_cell, const int *__restrict__ item_off,
                                                   const int *__restrict__ cell_start, const d4 *__restrict__ pq,
-                                                  uint16_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
+                                                  uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
 {
+    // neighbour ranges of the home cell: start, length, image shift and code
+    __shared__ int s_start[kStencil], s_len[kStencil], s_code[kStencil];
+    __shared__ double s_sx[kStencil], s_sy[kStencil], s_sz[kStencil];
     const int it = blockIdx.x;
     if (it >= *n_items) return;
     const int lane = (int)threadIdx.x;
@@ -106,6 +127,16 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     const int end = cell_start[c + 1];
     const int i0 = cell_start[c] + item_off[it];
     const int nh = (end - i0) < kPairHome ? (end - i0) : kPairHome;  // wave-uniform
+    for (int o = lane; o < kStencil; o += kLanes) {
+        double sx, sy, sz;
+        const int cn = neighbour(nc, L, cx, cy, cz, o, sx, sy, sz);
+        s_start[o] = cell_start[cn];
+        s_len[o] = cell_start[cn + 1] - s_start[o];
+        s_code[o] = shift_code(sx, sy, sz, L);
+        s_sx[o] = sx;
+        s_sy[o] = sy;
+        s_sz[o] = sz;
+    }
     double hx[kPairHome], hy[kPairHome], hz[kPairHome];
     int cnt[kPairHome];
 #pragma unroll
@@ -116,37 +147,28 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
         hz[h] = p.c;
         cnt[h] = 0;
     }
-    bool big = false;
-    for (int col = 0; col < 9; ++col) {
-        // the three cells of neighbour column col, as up to three ranges
-        int rs[3], rl[3], ro[3];
-        double rsx[3], rsy[3], rsz[3];
+    __syncthreads();
+    for (int col = 0; col < kSpan * kSpan; ++col) {
+        // the kSpan cells of neighbour column col, concatenated
+        int pre[kSpan];
         int tot = 0;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int o = col * 3 + t;
-            const int cn = neighbour(nc, L, cx, cy, cz, o, rsx[t], rsy[t], rsz[t]);
-            rs[t] = cell_start[cn];
-            rl[t] = cell_start[cn + 1] - rs[t];
-            ro[t] = o;
-            if (rl[t] > kPairMaxCell) {
-                big = true;
-                rl[t] = 0;
-            }
-            tot += rl[t];
+        for (int t = 0; t < kSpan; ++t) {
+            pre[t] = tot;
+            tot += s_len[col * kSpan + t];
         }
         for (int p0 = 0; p0 < tot; p0 += kLanes) {
             const int p = p0 + lane;
             const bool valid = p < tot;
-            const int t = p < rl[0] ? 0 : (p < rl[0] + rl[1] ? 1 : 2);
-            const int local = p - (t == 0 ? 0 : (t == 1 ? rl[0] : rl[0] + rl[1]));
-            const int j = (t == 0 ? rs[0] : (t == 1 ? rs[1] : rs[2])) + (valid ? local : 0);
-            const int o = t == 0 ? ro[0] : (t == 1 ? ro[1] : ro[2]);
-            const d4 q = pq[valid ? j : 0];
-            const double px = q.a + (t == 0 ? rsx[0] : (t == 1 ? rsx[1] : rsx[2]));
-            const double py = q.b + (t == 0 ? rsy[0] : (t == 1 ? rsy[1] : rsy[2]));
-            const double pz = q.c + (t == 0 ? rsz[0] : (t == 1 ? rsz[1] : rsz[2]));
-            const uint16_t entry = (uint16_t)((o << kPairLocalBits) | (valid ? local : 0));
+            int t = 0;
+#pragma unroll
+            for (int u = 1; u < kSpan; ++u) t += (p >= pre[u]) ? 1 : 0;
+            const int o = col * kSpan + t;
+            const int base = t == 0 ? pre[0] : (t == 1 ? pre[1] : (t == 2 ? pre[2] : (t == 3 ? pre[3] : pre[4])));
+            const int j = valid ? s_start[o] + (p - base) : 0;
+            const d4 q = pq[j];
+            const double px = q.a + s_sx[o], py = q.b + s_sy[o], pz = q.c + s_sz[o];
+            const uint32_t entry = (uint32_t)j | ((uint32_t)s_code[o] << kPairIndexBits);
 #pragma unroll
             for (int h = 0; h < kPairHome; ++h) {
                 if (h < nh) {
@@ -154,9 +176,10 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = valid && r2 < rc2 && !(o == kCenter && j == i0 + h);
                     const uint64_t m = __ballot(in);
-                    const int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi(
-                                                 (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    if (in && pos < cap) list[(size_t)(i0 + h) * cap + pos] = entry;
+                    int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                    pos = pos < cap ? pos : cap - 1;  // an overflowing list is not used
+                    if (in) list[(size_t)(i0 + h) * cap + pos] = entry;
                     cnt[h] += __popcll(m);
                 }
             }
@@ -167,61 +190,55 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
 #pragma unroll
         for (int h = 0; h < kPairHome; ++h)
             if (h == lane) v = cnt[h];
-        list_cnt[i0 + lane] = (big || v > cap) ? -1 : v;
+        list_cnt[i0 + lane] = v > cap ? -1 : v;
     }
 }
 
+// Evaluation pass: a work item is any kPairHome consecutive particles (lists
+// carry global indices and image-shift codes, so no per-cell table is needed).
 template <bool MIXED>
-__global__ __launch_bounds__(64) void k_pair(int nc, double L, double rc2, double alpha,
-                                             const int *__restrict__ n_items, const int *__restrict__ item_cell,
-                                             const int *__restrict__ item_off, const int *__restrict__ cell_start,
-                                             const d4 *__restrict__ pq, const uint16_t *__restrict__ list,
-                                             const int *__restrict__ list_cnt, int cap, d4 *__restrict__ freal)
+__global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double rc2, double alpha,
+                                             const int *__restrict__ cell_start, const d4 *__restrict__ pq,
+                                             const uint32_t *__restrict__ list, const int *__restrict__ list_cnt,
+                                             int cap, d4 *__restrict__ freal)
 {
     constexpr int kSub = kLanes / kPairHome;  // lanes per home particle
-    __shared__ int s_js[27];
-    __shared__ double s_sx[27], s_sy[27], s_sz[27];
-    const int it = blockIdx.x;
-    if (it >= *n_items) return;
+    __shared__ double s_sh[kStencil][3];
     const PairConsts k = pair_consts(alpha);
-    const int c = item_cell[it];
-    const int cx = c / (nc * nc), cy = (c / nc) % nc, cz = c % nc;
-    const int end = cell_start[c + 1];
     const int lane = (int)threadIdx.x;
-    const int h = lane / kSub, s = lane % kSub;
-    const int i = cell_start[c] + item_off[it] + h;
-    const bool act = i < end;
-    if (lane < 27) {
-        double sx, sy, sz;
-        const int cn = neighbour(nc, L, cx, cy, cz, lane, sx, sy, sz);
-        s_js[lane] = cell_start[cn];
-        s_sx[lane] = sx;
-        s_sy[lane] = sy;
-        s_sz[lane] = sz;
+    for (int code = lane; code < kStencil; code += kLanes) {
+        s_sh[code][0] = (double)(code / (kSpan * kSpan) - kPairReach) * L;
+        s_sh[code][1] = (double)((code / kSpan) % kSpan - kPairReach) * L;
+        s_sh[code][2] = (double)(code % kSpan - kPairReach) * L;
     }
     __syncthreads();
+    const int h = lane / kSub, s = lane % kSub;
+    const int64_t i = (int64_t)blockIdx.x * kPairHome + h;
+    const bool act = i < n;
     const d4 me = pq[act ? i : 0];
     const int cnt = act ? list_cnt[i] : 0;
     double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    const uint16_t *mine = list + (size_t)(act ? i : 0) * cap;
+    const uint32_t *mine = list + (size_t)(act ? i : 0) * cap;
     for (int r = s; __any(r < cnt); r += kSub) {
         if (r < cnt) {
-            const unsigned e = mine[r];
-            const int o = (int)(e >> kPairLocalBits);
-            const d4 p = pq[s_js[o] + (int)(e & (kPairMaxCell - 1))];
-            const double dx = (me.a - s_sx[o]) - p.a;
-            const double dy = (me.b - s_sy[o]) - p.b;
-            const double dz = (me.c - s_sz[o]) - p.c;
+            const uint32_t e = mine[r];
+            const int code = (int)(e >> kPairIndexBits);
+            const d4 p = pq[e & ((1u << kPairIndexBits) - 1)];
+            const double dx = (me.a - s_sh[code][0]) - p.a;
+            const double dy = (me.b - s_sh[code][1]) - p.b;
+            const double dz = (me.c - s_sh[code][2]) - p.c;
             pair_term<MIXED>(dx, dy, dz, dx * dx + dy * dy + dz * dz, p.d, k, ph, fx, fy, fz);
         }
     }
     if (__any(cnt < 0)) {
-        // exact direct loop for particles whose list overflowed; sub-lane s
-        // takes the neighbour offsets o = s, s + kSub, ...
+        // exact direct loop for particles whose list overflowed; sub-lane s takes
+        // the neighbour offsets o = s, s + kSub, ...
         const bool slow = cnt < 0;
-        for (int o = s; o < 27; o += kSub) {
+        const int cx = (int)(me.a * nc / L), cy = (int)(me.b * nc / L), cz = (int)(me.c * nc / L);
+        const int hx = cx < nc ? cx : nc - 1, hy = cy < nc ? cy : nc - 1, hz = cz < nc ? cz : nc - 1;
+        for (int o = s; o < kStencil; o += kSub) {
             double sx, sy, sz;
-            const int cn = neighbour(nc, L, cx, cy, cz, o, sx, sy, sz);
+            const int cn = neighbour(nc, L, hx, hy, hz, o, sx, sy, sz);
             const double xi = me.a - sx, yi = me.b - sy, zi = me.c - sz;
             const int js = cell_start[cn], je = cell_start[cn + 1];
             for (int j = js; slow && j < je; ++j) {
@@ -254,23 +271,23 @@ __global__ __launch_bounds__(64) void k_pair(int nc, double L, double rc2, doubl
 
 hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, const int *n_items,
                             const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
-                            uint16_t *list, int *list_cnt, int cap)
+                            uint32_t *list, int *list_cnt, int cap)
 {
     hipLaunchKernelGGL(k_pair_list, dim3(max_items), dim3(64), 0, s, a.nc, a.L, a.rc2, n_items, item_cell, item_off,
                        cell_start, pq, list, list_cnt, cap);
     return hipGetLastError();
 }
 
-hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, int max_items, const int *n_items,
-                       const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
-                       const uint16_t *list, const int *list_cnt, int cap, d4 *freal)
+hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *cell_start, const d4 *pq,
+                       const uint32_t *list, const int *list_cnt, int cap, d4 *freal)
 {
+    const int blocks = ceil_div(a.n, kPairHome);
     if (mixed)
-        hipLaunchKernelGGL(k_pair<true>, dim3(max_items), dim3(64), 0, s, a.nc, a.L, a.rc2, a.alpha, n_items,
-                           item_cell, item_off, cell_start, pq, list, list_cnt, cap, freal);
+        hipLaunchKernelGGL(k_pair<true>, dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq,
+                           list, list_cnt, cap, freal);
     else
-        hipLaunchKernelGGL(k_pair<false>, dim3(max_items), dim3(64), 0, s, a.nc, a.L, a.rc2, a.alpha, n_items,
-                           item_cell, item_off, cell_start, pq, list, list_cnt, cap, freal);
+        hipLaunchKernelGGL(k_pair<false>, dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq,
+                           list, list_cnt, cap, freal);
     return hipGetLastError();
 }
 

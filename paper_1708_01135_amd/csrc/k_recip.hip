@@ -267,6 +267,8 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
 }
 
 // ------------------------------------------------------------- k_sk_reduce
+constexpr int kRedLanes = kRedSlotLanes;  // lanes cooperating on one slot
+
 template <typename R>
 __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, int n_rows, const d4 *__restrict__ part,
                                                    const int *__restrict__ unit_group,
@@ -278,21 +280,32 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
 {
     __shared__ double s_e[256];
     const int n_slots = n_units * kQ * kLanes;
-    const int slot = blockIdx.x * 256 + threadIdx.x;
+    // kRedLanes lanes per slot: lane c sums chunks c, c + kRedLanes, ...; the
+    // partial sums are then combined by a fixed xor-shuffle tree
+    const int sub = threadIdx.x % kRedLanes;
+    const int slot = blockIdx.x * (256 / kRedLanes) + threadIdx.x / kRedLanes;
+    const int cslot = slot < n_slots ? slot : n_slots - 1;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int c = sub; c < n_chunks; c += kRedLanes) {
+        const d4 p = part[(size_t)c * n_slots + cslot];
+        s0 += p.a;
+        s1 += p.b;
+        s2 += p.c;
+        s3 += p.d;
+    }
+#pragma unroll
+    for (int w = 1; w < kRedLanes; w <<= 1) {
+        s0 += __shfl_xor(s0, w);
+        s1 += __shfl_xor(s1, w);
+        s2 += __shfl_xor(s2, w);
+        s3 += __shfl_xor(s3, w);
+    }
     double e = 0.0;
-    if (slot < n_slots) {
+    if (slot < n_slots && sub == 0) {
         const int lane = slot & (kLanes - 1);
         const int uq = slot / kLanes;
         const int k = uq % kQ;
         const int u = uq / kQ;
-        double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-        for (int c = 0; c < n_chunks; ++c) {
-            const d4 p = part[(size_t)c * n_slots + slot];
-            s0 += p.a;
-            s1 += p.b;
-            s2 += p.c;
-            s3 += p.d;
-        }
         const int seg = unit_seg[u];
         const int r = unit_group[u] * kLanes + lane;
         const int a = seg * kQ + k;
@@ -511,7 +524,7 @@ hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, con
                             const int *unit_seg, const int *row_nx, const int *row_ny, const int *row_m,
                             const int *row_item, const double *ck, d4 *sk, R *rec, double *erec_part)
 {
-    hipLaunchKernelGGL(k_sk_reduce<R>, dim3(ceil_div(a.n_slots, 256)), dim3(256), 0, s, n_chunks, a.n_units,
+    hipLaunchKernelGGL(k_sk_reduce<R>, dim3(ceil_div(a.n_slots, 256 / kRedLanes)), dim3(256), 0, s, n_chunks, a.n_units,
                        a.n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec,
                        erec_part);
     return hipGetLastError();

@@ -111,12 +111,13 @@ void build_klayout(int K, KLayout &kl)
         kl.item_meta[i] = (kl.item_seg[i] << 16) | (kl.item_nx[i] << 8) | (kl.item_ny[i] + 128);
 }
 
+// Cells per axis for the pair loop: side h = L / nc >= r_c / kPairReach.
 int cells_per_axis(double L, double rc)
 {
-    double f = std::floor(L / rc);
+    const double f = std::floor(kPairReach * L / rc);
     int nc = f < 1.0 ? 1 : (f > kMaxCellsPerAxis ? kMaxCellsPerAxis : (int)f);
-    // guard against L/rc rounding just above an integer: h must stay >= rc
-    while (nc > 1 && L / nc < rc) --nc;
+    // guard against rounding just above an integer: h * kPairReach must stay >= rc
+    while (nc > 1 && (L / nc) * kPairReach < rc) --nc;
     return nc;
 }
 
@@ -187,7 +188,7 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.qpart = align_up(sizeof(double) * 2 * (size_t)bin_blocks(N));
     z.scalars = align_up(sizeof(double) * 4);
     z.epart = align_up(sizeof(double) * (size_t)ceil_div(N, 256));
-    z.erec = align_up(sizeof(double) * (size_t)ceil_div((int64_t)n_slots, 256));
+    z.erec = align_up(sizeof(double) * (size_t)ceil_div((int64_t)n_slots, 256 / kRedSlotLanes));
     z.ck = align_up(sizeof(double) * ((size_t)kl.K * kl.K + 1));
     z.tx = align_up(creal * (size_t)N * kl.KP);
     z.part = align_up(sizeof(d4) * (size_t)z.max_chunks * n_slots);
@@ -202,7 +203,7 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.list_cap = pair_list_cap(p);
     z.pitem_cell = z.pitem_off = align_up(sizeof(int) * (size_t)z.max_pitems);
     z.n_pitems = align_up(sizeof(int));
-    z.plist = align_up(sizeof(uint16_t) * (size_t)z.list_cap * N);
+    z.plist = align_up(sizeof(uint32_t) * (size_t)z.list_cap * N);
     z.plist_cnt = align_up(sizeof(int) * N);
     z.total = 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
               z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
@@ -235,7 +236,7 @@ struct ewald_plan_s {
     int *row_nx = nullptr, *row_ny = nullptr, *row_m = nullptr, *unit_g = nullptr, *unit_s = nullptr,
         *row_item = nullptr, *item_nx = nullptr, *item_ny = nullptr, *item_seg = nullptr;
     int *pitem_cell = nullptr, *pitem_off = nullptr, *n_pitems = nullptr, *plist_cnt = nullptr;
-    uint16_t *plist = nullptr;
+    uint32_t *plist = nullptr;
     // profiling
     bool prof = false;
     std::vector<ProfRec> pending;
@@ -339,7 +340,7 @@ const char *ewald_status_string(ewald_status s)
 ewald_status ewald_params_validate(const ewald_params *p)
 {
     if (!p) return EWALD_ERR_INVALID_ARG;
-    if (p->n_max < 1 || p->n_max > ((int64_t)1 << 30)) return EWALD_ERR_INVALID_ARG;
+    if (p->n_max < 1 || p->n_max > kPairMaxN) return EWALD_ERR_INVALID_ARG;
     if (!(std::isfinite(p->box_L) && p->box_L > 0.0)) return EWALD_ERR_INVALID_ARG;
     if (!(std::isfinite(p->alpha) && p->alpha > 0.0)) return EWALD_ERR_INVALID_ARG;
     if (!(std::isfinite(p->r_c) && p->r_c > 0.0 && p->r_c <= p->box_L)) return EWALD_ERR_INVALID_ARG;
@@ -441,7 +442,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->pitem_cell = carve<int>(cur, z.pitem_cell);
     p->pitem_off = carve<int>(cur, z.pitem_off);
     p->n_pitems = carve<int>(cur, z.n_pitems);
-    p->plist = carve<uint16_t>(cur, z.plist);
+    p->plist = carve<uint32_t>(cur, z.plist);
     p->plist_cnt = carve<int>(cur, z.plist_cnt);
 
     // C_k by integer |n|^2 (computed once on the host in FP64)
@@ -507,7 +508,7 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
     const int n_split = gather_split(n);
     SplitTable st{};
     for (int k = 0; k <= n_split; ++k) st.lo[k] = (int)((int64_t)kl.n_items * k / n_split);
-    FinalArgs fa{n, L, p->prm.alpha, n_split, ceil_div((int64_t)ra.n_slots, 256)};
+    FinalArgs fa{n, L, p->prm.alpha, n_split, ceil_div((int64_t)ra.n_slots, 256 / kRedSlotLanes)};
     const int nqb = bin_blocks(n);
 
     hipError_t e = hipSuccess;
@@ -560,8 +561,7 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
                                 p->plist, p->plist_cnt, p->sz.list_cap);
     });
     run(KC_PAIR, [&] {
-        return launch_pair(s, pa, p->mixed, max_pitems, p->n_pitems, p->pitem_cell, p->pitem_off, p->cell_start,
-                           p->pq, p->plist, p->plist_cnt, p->sz.list_cap, p->freal);
+        return launch_pair(s, pa, p->mixed, p->cell_start, p->pq, p->plist, p->plist_cnt, p->sz.list_cap, p->freal);
     });
     run(KC_FINAL_P, [&] {
         return launch_finalize_particles(s, fa, p->pq, p->perm, p->freal, p->gpart, p->scalars, forces, dEdq,
