@@ -155,4 +155,17 @@ hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const doubl
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// MI355X dispatches the workgroups of a launch to its 8 XCDs round-robin by
+// linear block id, and each XCD has its own L2.  Kernels whose neighbouring
+// work items share data launch xcd_grid(n) blocks and map the hardware id
+// through xcd_remap(), which gives every XCD a contiguous range of logical
+// blocks; logical ids >= n are padding and exit at once.
+constexpr int kXcds = 8;
+inline int xcd_grid(int n) { return ceil_div(n, kXcds) * kXcds; }
+__device__ inline int xcd_remap(int b, int n)
+{
+    const int per = (n + kXcds - 1) / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+
 }  // namespace ewk

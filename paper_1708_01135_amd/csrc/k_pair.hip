@@ -111,7 +111,8 @@ __device__ inline int shift_code(double sx, double sy, double sz, double L)
     return (ix * kSpan + iy) * kSpan + iz;
 }
 
-__global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, const int *__restrict__ n_items,
+__global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
+                                                  const int *__restrict__ n_items,
                                                   const int *__restrict__ item_cell, const int *__restrict__ item_off,
                                                   const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                                   uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
@@ -119,8 +120,14 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     // neighbour ranges of the home cell: start, length, image shift and code
     __shared__ int s_start[kStencil], s_len[kStencil], s_code[kStencil];
     __shared__ double s_sx[kStencil], s_sy[kStencil], s_sz[kStencil];
-    const int it = blockIdx.x;
-    if (it >= *n_items) return;
+    // neighbouring cells share one XCD's L2: remap over the actual item count
+    // (known on the device only), so that padding blocks do not pile up on one XCD
+    const int nit = *n_items;
+    const int per = (nit + kXcds - 1) / kXcds;
+    if ((int)blockIdx.x >= per * kXcds) return;
+    const int it = xcd_remap(blockIdx.x, nit);
+    if (it >= nit) return;
+    (void)max_items;
     const int lane = (int)threadIdx.x;
     const int c = item_cell[it];
     const int cx = c / (nc * nc), cy = (c / nc) % nc, cz = c % nc;
@@ -213,7 +220,8 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
     }
     __syncthreads();
     const int h = lane / kSub, s = lane % kSub;
-    const int64_t i = (int64_t)blockIdx.x * kPairHome + h;
+    const int blocks = (int)((n + kPairHome - 1) / kPairHome);
+    const int64_t i = (int64_t)xcd_remap(blockIdx.x, blocks) * kPairHome + h;
     const bool act = i < n;
     const d4 me = pq[act ? i : 0];
     const int cnt = act ? list_cnt[i] : 0;
@@ -273,15 +281,15 @@ hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, con
                             const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
                             uint32_t *list, int *list_cnt, int cap)
 {
-    hipLaunchKernelGGL(k_pair_list, dim3(max_items), dim3(64), 0, s, a.nc, a.L, a.rc2, n_items, item_cell, item_off,
-                       cell_start, pq, list, list_cnt, cap);
+    hipLaunchKernelGGL(k_pair_list, dim3(xcd_grid(max_items)), dim3(64), 0, s, a.nc, a.L, a.rc2, max_items, n_items,
+                       item_cell, item_off, cell_start, pq, list, list_cnt, cap);
     return hipGetLastError();
 }
 
 hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *cell_start, const d4 *pq,
                        const uint32_t *list, const int *list_cnt, int cap, d4 *freal)
 {
-    const int blocks = ceil_div(a.n, kPairHome);
+    const int blocks = xcd_grid(ceil_div(a.n, kPairHome));
     if (mixed)
         hipLaunchKernelGGL(k_pair<true>, dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq,
                            list, list_cnt, cap, freal);

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
                                                          const int *__restrict__ unit_seg,
                                                          const int *__restrict__ row_nx,
                                                          const int *__restrict__ row_ny, int n_rows, int n_units,
-                                                         d4 *__restrict__ part)
+                                                         int n_chunks, d4 *__restrict__ part)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     const int lane = threadIdx.x & (kLanes - 1);
@@ -143,7 +143,12 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
     c64 *buf = reinterpret_cast<c64 *>(smem) + (size_t)wave * 2 * per_tile;  // two buffers
     d4 *red = reinterpret_cast<d4 *>(smem);
 
-    const int u = blockIdx.x;
+    // logical block = chunk * n_units + unit, placed so that all units of a
+    // chunk (which share its phase tables) run on one XCD
+    const int lb = xcd_remap(blockIdx.x, n_units * n_chunks);
+    if (lb >= n_units * n_chunks) return;
+    const int u = lb % n_units;
+    const int chunk = lb / n_units;
     const int seg = unit_seg[u];
     const int r = unit_group[u] * kLanes + lane;
     int nx = 0, ny = 0;
@@ -153,7 +158,7 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
     }
     const int ay = K1 + (ny < 0 ? -ny : ny);  // y entries follow the x entries of a particle
     const double ysign = ny < 0 ? -1.0 : 1.0;
-    const int64_t j0 = (int64_t)blockIdx.y * chunk_len;
+    const int64_t j0 = (int64_t)chunk * chunk_len;
     const int64_t j1 = (j0 + chunk_len < n) ? j0 + chunk_len : n;
     const int n_tiles = j1 > j0 ? (int)((j1 - j0 + ts - 1) / ts) : 0;
 
@@ -260,7 +265,7 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
         }
     }
     if (wave == 0) {
-        d4 *dst = part + ((size_t)blockIdx.y * n_units + u) * kQ * kLanes + lane;
+        d4 *dst = part + ((size_t)chunk * n_units + u) * kQ * kLanes + lane;
 #pragma unroll
         for (int k = 0; k < kQ; ++k) dst[k * kLanes] = mine[k];
     }
@@ -513,9 +518,9 @@ hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_
 {
     const int K1 = a.K + 1;
     const int ts = sk_tile(K1);
-    hipLaunchKernelGGL(k_sk, dim3(a.n_units, n_chunks), dim3(kSkWaves * kLanes), sk_smem_bytes(ts, K1), s, a.n,
-                       chunk_len, ts, a.KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, a.n_rows, a.n_units,
-                       part);
+    hipLaunchKernelGGL(k_sk, dim3(xcd_grid(a.n_units * n_chunks)), dim3(kSkWaves * kLanes), sk_smem_bytes(ts, K1), s,
+                       a.n, chunk_len, ts, a.KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, a.n_rows,
+                       a.n_units, n_chunks, part);
     return hipGetLastError();
 }
 
