@@ -133,6 +133,22 @@ ewald_status ewald_plan_set_stream(ewald_plan_t plan, void *stream);
 ewald_status ewald_energy_forces(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
                                  double *energy, double *forces, double *dEdq);
 
+/* Energy only (the forward of the adjoint pair below): same arguments and
+ * errors as ewald_energy_forces without force / dE/dq outputs.  The force
+ * gather is skipped; the reciprocal energy comes from the structure factor. */
+ewald_status ewald_energy(ewald_plan_t plan, int64_t n, const double *pos, const double *q, double *energy);
+
+/* Adjoint of E(pos, q) for an upstream gradient g = dL/dE:
+ *   grad_energy  device, 1 double: g (read on the device, no host sync).
+ *   energy       device, 5 doubles: the energy parts, recomputed.
+ *   grad_pos     device, n x 3: dL/dr_i = -g F_i, or NULL to skip.
+ *   grad_q       device, n: dL/dq_i = g dE/dq_i, or NULL to skip.
+ * The phases and S(k) are recomputed from pos and q (nothing per particle and
+ * k vector is stored between the forward and this call).  Errors as
+ * ewald_energy_forces, plus INVALID_ARG for a NULL grad_energy. */
+ewald_status ewald_energy_backward(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
+                                   const double *grad_energy, double *energy, double *grad_pos, double *grad_q);
+
 /* Synchronise the plan's stream, then return and clear the status latched by
  * device-side checks (EWALD_OK if none). */
 ewald_status ewald_plan_status(ewald_plan_t plan);

@@ -143,8 +143,9 @@ struct FinalArgs {
     int64_t n;
     double L;
     double alpha;
-    int n_split;
+    int n_split;           // gather partials to sum (0: energy only)
     int n_erec;
+    const double *gscale;  // device scalar g (or null): forces := -g F, dEdq := g dE/dq
 };
 hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
                                      const d4 *freal, const d4 *gpart, const double *scalars,

@@ -1,5 +1,7 @@
 // Totals and output (section 3.2.2 for the self term):
 //   F_i      = F_real,i + q_i (2 pi / L) sum_splits g_i            (caller order)
+//   with an upstream gradient g (device scalar) the outputs become the adjoint
+//   dL/dr_i = -g F_i and dL/dq_i = g dE/dq_i.
 //   dE/dq_i  = phi_real,i + phi_recip,i - 2 sqrt(alpha/pi) q_i - pi Q / (V alpha)
 //   E_real   = 1/2 sum_i q_i phi_real,i
 //   E_self   = -sqrt(alpha/pi) sum q_i^2,   E_bg = -pi Q^2 / (2 V alpha)
@@ -15,8 +17,9 @@ constexpr double kPi = 3.14159265358979323846264338327950288;
 __global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alpha, int n_split,
                                                  const d4 *__restrict__ pq, const int *__restrict__ perm,
                                                  const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
-                                                 const double *__restrict__ scalars, double *__restrict__ forces,
-                                                 double *__restrict__ dEdq, double *__restrict__ epart)
+                                                 const double *__restrict__ scalars, const double *__restrict__ gscale,
+                                                 double *__restrict__ forces, double *__restrict__ dEdq,
+                                                 double *__restrict__ epart)
 {
     __shared__ double s_e[256];
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -34,14 +37,16 @@ __global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alp
         const double q = pq[s].d;
         const double kf = q * (2.0 * kPi / L);
         const int64_t i = perm[s];
+        const double gs = gscale ? *gscale : 1.0;
+        const double fs = gscale ? -gs : 1.0;
         if (forces) {
-            forces[3 * i] = fr.b + kf * g1;
-            forces[3 * i + 1] = fr.c + kf * g2;
-            forces[3 * i + 2] = fr.d + kf * g3;
+            forces[3 * i] = fs * (fr.b + kf * g1);
+            forces[3 * i + 1] = fs * (fr.c + kf * g2);
+            forces[3 * i + 2] = fs * (fr.d + kf * g3);
         }
         if (dEdq) {
             const double V = L * L * L;
-            dEdq[i] = fr.a + g0 - 2.0 * sqrt(alpha / kPi) * q - kPi * scalars[0] / (V * alpha);
+            dEdq[i] = gs * (fr.a + g0 - 2.0 * sqrt(alpha / kPi) * q - kPi * scalars[0] / (V * alpha));
         }
         e = 0.5 * q * fr.a;
     }
@@ -108,7 +113,7 @@ hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4
                                      double *dEdq, double *epart)
 {
     hipLaunchKernelGGL(k_final_p, dim3(ceil_div(a.n, 256)), dim3(256), 0, s, a.n, a.L, a.alpha, a.n_split, pq, perm,
-                       freal, gpart, scalars, forces, dEdq, epart);
+                       freal, gpart, scalars, a.gscale, forces, dEdq, epart);
     return hipGetLastError();
 }
 

@@ -489,10 +489,16 @@ ewald_status ewald_plan_set_stream(ewald_plan_t plan, void *stream)
     return EWALD_OK;
 }
 
-ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy,
-                                 double *forces, double *dEdq)
+}  // extern "C"
+
+namespace {
+
+// The whole evaluation on the plan's stream.  energy_only skips the force
+// gather (the reciprocal energy comes from the structure factor alone);
+// gscale, when given, turns the force / dE/dq outputs into the adjoint.
+ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy, double *forces,
+                      double *dEdq, const double *gscale, bool energy_only)
 {
-    if (!p || !pos || !q || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
     if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
     DeviceGuard dg(p->device);
     if (!dg.ok()) return EWALD_ERR_DEVICE;
@@ -508,7 +514,8 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
     const int n_split = gather_split(n);
     SplitTable st{};
     for (int k = 0; k <= n_split; ++k) st.lo[k] = (int)((int64_t)kl.n_items * k / n_split);
-    FinalArgs fa{n, L, p->prm.alpha, n_split, ceil_div((int64_t)ra.n_slots, 256 / kRedSlotLanes)};
+    FinalArgs fa{n, L, p->prm.alpha, energy_only ? 0 : n_split, ceil_div((int64_t)ra.n_slots, 256 / kRedSlotLanes),
+                 gscale};
     const int nqb = bin_blocks(n);
 
     hipError_t e = hipSuccess;
@@ -539,7 +546,7 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
                                                p->row_ny, p->row_m, p->row_item, p->ck, p->sk,
                                                static_cast<float *>(p->rec), p->erec);
             });
-            run(KC_GATHER, [&] {
+            if (!energy_only) run(KC_GATHER, [&] {
                 return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_seg,
                                             static_cast<const float *>(p->rec), p->gpart);
             });
@@ -549,7 +556,7 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
                                                 p->row_ny, p->row_m, p->row_item, p->ck, p->sk,
                                                 static_cast<double *>(p->rec), p->erec);
             });
-            run(KC_GATHER, [&] {
+            if (!energy_only) run(KC_GATHER, [&] {
                 return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_seg,
                                              static_cast<const double *>(p->rec), p->gpart);
             });
@@ -575,6 +582,33 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
         return EWALD_ERR_DEVICE;
     }
     return EWALD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy,
+                                 double *forces, double *dEdq)
+{
+    if (!p || !pos || !q || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    return run_path(p, n, pos, q, energy, forces, dEdq, nullptr, false);
+}
+
+ewald_status ewald_energy(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy)
+{
+    if (!p || !pos || !q || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    return run_path(p, n, pos, q, energy, nullptr, nullptr, nullptr, true);
+}
+
+ewald_status ewald_energy_backward(ewald_plan_t p, int64_t n, const double *pos, const double *q,
+                                   const double *grad_energy, double *energy, double *grad_pos, double *grad_q)
+{
+    if (!p || !pos || !q || !grad_energy || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    return run_path(p, n, pos, q, energy, grad_pos, grad_q, grad_energy, false);
 }
 
 ewald_status ewald_plan_status(ewald_plan_t p)

@@ -68,6 +68,10 @@ def _load():
     lib.ewald_plan_set_stream.argtypes = [vp, vp]
     lib.ewald_energy_forces.restype = ctypes.c_int
     lib.ewald_energy_forces.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    lib.ewald_energy.restype = ctypes.c_int
+    lib.ewald_energy.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+    lib.ewald_energy_backward.restype = ctypes.c_int
+    lib.ewald_energy_backward.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
     lib.ewald_plan_status.restype = ctypes.c_int
     lib.ewald_plan_status.argtypes = [vp]
     lib.ewald_release.restype = None
@@ -177,6 +181,42 @@ class Plan:
             raise EwaldError(st, "ewald_energy_forces")
         return e, f, g
 
+    def _check_inputs(self, pos, q):
+        import torch
+        n = int(q.shape[0])
+        for name, t, shape in (("pos", pos, (n, 3)), ("q", q, (n,))):
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        st = _load().ewald_plan_set_stream(self.handle, _stream_handle())
+        if st != OK:
+            raise EwaldError(st, "ewald_plan_set_stream")
+        return n
+
+    def energy(self, pos, q):
+        """Energy parts (5,) only; the force gather is skipped."""
+        import torch
+        n = self._check_inputs(pos, q)
+        e = torch.empty(5, dtype=torch.float64, device=pos.device)
+        st = _load().ewald_energy(self.handle, n, pos.data_ptr(), q.data_ptr(), e.data_ptr())
+        if st != OK:
+            raise EwaldError(st, "ewald_energy")
+        return e
+
+    def energy_backward(self, pos, q, grad_energy, need_pos=True, need_q=True):
+        """(dL/dpos, dL/dq) for the upstream gradient ``grad_energy`` (device scalar)."""
+        import torch
+        n = self._check_inputs(pos, q)
+        g = grad_energy.detach().to(dtype=torch.float64).reshape(1).contiguous()
+        e = torch.empty(5, dtype=torch.float64, device=pos.device)
+        gp = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if need_pos else None
+        gq = torch.empty(n, dtype=torch.float64, device=pos.device) if need_q else None
+        st = _load().ewald_energy_backward(self.handle, n, pos.data_ptr(), q.data_ptr(), g.data_ptr(), e.data_ptr(),
+                                           gp.data_ptr() if gp is not None else None,
+                                           gq.data_ptr() if gq is not None else None)
+        if st != OK:
+            raise EwaldError(st, "ewald_energy_backward")
+        return gp, gq
+
     def status(self) -> int:
         return int(_load().ewald_plan_status(self.handle))
 
@@ -234,3 +274,38 @@ def energy_forces(pos, q, box_L, alpha, r_c, k_max, precision="fp64", dEdq=False
     """One-shot evaluation (builds and releases a plan)."""
     with Plan(int(q.shape[0]), box_L, alpha, r_c, k_max, precision, pos.device.index or 0) as p:
         return p.energy_forces(pos, q, True, dEdq)
+
+
+def _autograd_function():
+    import torch
+
+    class EwaldEnergy(torch.autograd.Function):
+        """E(pos, q) as a differentiable scalar: the forward runs the energy-only
+        path; the backward runs the library's adjoint (recomputing phases and
+        S(k)) and returns dL/dpos = -g F and dL/dq = g dE/dq."""
+
+        @staticmethod
+        def forward(ctx, pos, q, plan):
+            ctx.plan = plan
+            ctx.save_for_backward(pos, q)
+            return plan.energy(pos.detach().contiguous(), q.detach().contiguous())[0]
+
+        @staticmethod
+        def backward(ctx, g):
+            pos, q = ctx.saved_tensors
+            gp, gq = ctx.plan.energy_backward(pos.detach().contiguous(), q.detach().contiguous(), g,
+                                              ctx.needs_input_grad[0], ctx.needs_input_grad[1])
+            return gp, gq, None
+
+    return EwaldEnergy
+
+
+_EwaldEnergy = None
+
+
+def ewald_energy(pos, q, plan: "Plan"):
+    """Differentiable Ewald energy (scalar tensor) for ``plan``."""
+    global _EwaldEnergy
+    if _EwaldEnergy is None:
+        _EwaldEnergy = _autograd_function()
+    return _EwaldEnergy.apply(pos, q, plan)
