@@ -10,8 +10,10 @@ totals) with inputs resident in HBM.
 Prints one JSON line: the mixed-precision throughput as ``value`` (particle
 evaluations per second), the plain-FP64 throughput beside it, p50/p99 latency,
 errors of both paths against the FP64 CPU oracle, the roofline of the dominant
-kernel (per-kernel HIP-event timing on the plan's stream) and the oracle's own
-throughput on this host.
+kernel (per-kernel HIP-event timing on the plan's stream), the oracle's own
+throughput on this host and, under ``serving``, the request server on a mix of
+256 independent electrolyte systems (N = 500 ... 50000, K = 9 ... 41): its
+saturation throughput and p50/p99 latency under Poisson arrivals.
 """
 import argparse
 import hashlib
@@ -49,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--serving-systems", type=int, default=256)
+    ap.add_argument("--serving-passes", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -134,6 +139,88 @@ def latencies(plan, pos, q, out, calls):
             "calls": calls}
 
 
+def pct(sorted_ms, p):
+    return sorted_ms[min(len(sorted_ms) - 1, max(0, int(math.ceil(p * len(sorted_ms))) - 1))]
+
+
+def serving(n_systems, passes):
+    """Request server on independent electrolyte systems (density 0.8, r_c = 4.5,
+    alpha r_c^2 = 14.4, K matched to the real-space exponent): saturation throughput
+    with every request submitted at once, then Poisson arrivals at fractions of it.
+    Latency = completion observed by the server minus the scheduled arrival."""
+    import numpy as np
+    import torch
+
+    from paper_1708_01135_amd import ewald, workloads
+    t_gen = time.perf_counter()
+    mix = workloads.serving_mix(n_systems, seed=0, workers=min(16, os.cpu_count() or 1))
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    pos = [torch.tensor(it["pos"], device=dev) for it in mix]
+    q = [torch.tensor(it["q"], device=dev) for it in mix]
+    outs = [(torch.empty(5, dtype=torch.float64, device=dev), torch.empty((it["n"], 3), dtype=torch.float64, device=dev),
+             None) for it in mix]
+    torch.cuda.synchronize()
+    ns = np.array([it["n"] for it in mix])
+    units = float(sum(it["n"] * ewald.kset_size(it["k_max"]) for it in mix))
+    res = {"systems": n_systems, "n_total": int(ns.sum()), "n_range": [int(ns.min()), int(ns.max())],
+           "k_range": [min(it["k_max"] for it in mix), max(it["k_max"] for it in mix)], "precision": "mixed",
+           "generate_s": round(t_gen, 1)}
+
+    def saturate(srv, ids):
+        t0 = time.perf_counter()
+        tick = [srv.submit(ids[s], pos[s], q[s], out=outs[s]) for s in range(n_systems)]
+        for t in tick:
+            srv.wait(t)
+        return time.perf_counter() - t0
+
+    def run(srv, ids):
+        saturate(srv, ids)  # warm-up
+        return min(saturate(srv, ids) for _ in range(3))
+
+    with ewald.Server(n_streams=1, precision="mixed") as srv:
+        ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
+        t1 = run(srv, ids)
+    with ewald.Server(n_streams=4, precision="mixed") as srv:
+        t_add = time.perf_counter()
+        ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
+        t_add = time.perf_counter() - t_add
+        res["workspace_gb"] = round(srv.stats()["used"] / 1e9, 2)
+        res["register_s"] = round(t_add, 2)
+        t4 = run(srv, ids)
+        sat = n_systems / t4
+        res["saturation"] = {"streams_4": {"systems_per_s": sat, "particle_evals_per_s": ns.sum() / t4,
+                                           "tflops_alg": 30.0 * units / t4 / 1e12},
+                             "streams_1": {"systems_per_s": n_systems / t1, "particle_evals_per_s": ns.sum() / t1}}
+        rng = np.random.default_rng(1000)
+        res["poisson"] = []
+        for frac in (0.25, 0.5, 0.7, 0.9):
+            rate = frac * sat
+            seq = np.concatenate([rng.permutation(n_systems) for _ in range(passes)])
+            arrive = np.cumsum(rng.exponential(1.0 / rate, size=seq.size))
+            t0 = ewald.Server.clock()
+            tick = []
+            for s, ta in zip(seq, arrive):
+                while ewald.Server.clock() - t0 < ta:
+                    pass
+                tick.append((t0 + ta, srv.submit(ids[s], pos[s], q[s], out=outs[s])))
+            lat = []
+            t_end = t0
+            for ta, t in tick:
+                _, _, td = srv.wait(t)
+                lat.append((td - ta) * 1e3)
+                t_end = max(t_end, td)
+            lat.sort()
+            res["poisson"].append({"load": frac, "rate_per_s": rate, "requests": int(seq.size),
+                                   "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "max_ms": lat[-1],
+                                   "achieved_per_s": seq.size / (t_end - t0)})
+            print(f"serving load {frac}: p50 {pct(lat, 0.5):.3f} ms p99 {pct(lat, 0.99):.3f} ms", file=sys.stderr,
+                  flush=True)
+        for i in ids:
+            assert srv.system_status(i) == ewald.OK
+    return res
+
+
 def main():
     args = parse()
     if args.calib_copy_mib:
@@ -202,6 +289,9 @@ def main():
                 "frac": ach / PEAK_TFLOPS, "traffic": traffic_bytes(dom, args.workload, head_prec),
                 "avg_ms": kern[dom]["avg_ms"], "algorithmic_flops_per_launch": flops,
                 "frac_of_published_fp32_peak": ach / PEAK_FP32_PUBLISHED if head_prec == "mixed" else None}
+    serve = None
+    if not args.no_serving:
+        serve = serving(args.serving_systems, args.serving_passes)
     line = {
         "metric": METRIC,
         "value": head["pe_s"],
@@ -227,6 +317,7 @@ def main():
         "kernels_ms": {p: {k: round(v["avg_ms"], 5) for k, v in r["kernels"].items()} for p, r in results.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "serving": serve,
     }
     print(json.dumps(line), flush=True)
 

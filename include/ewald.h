@@ -56,7 +56,8 @@ typedef enum {
     EWALD_ERR_CAPACITY = -2,      /* n exceeds the plan's n_max                   */
     EWALD_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed             */
     EWALD_ERR_DEVICE = -4,        /* a HIP runtime call or kernel launch failed   */
-    EWALD_ERR_NONFINITE = -5      /* a position or charge was NaN or infinite     */
+    EWALD_ERR_NONFINITE = -5,     /* a position or charge was NaN or infinite     */
+    EWALD_ERR_ADMISSION = -6      /* workspace above a server's free HBM budget   */
 } ewald_status;
 
 /* Arithmetic of the hot kernels. */

@@ -333,6 +333,7 @@ const char *ewald_status_string(ewald_status s)
     case EWALD_ERR_OUT_OF_MEMORY: return "out of memory";
     case EWALD_ERR_DEVICE: return "HIP device or launch error";
     case EWALD_ERR_NONFINITE: return "non-finite position or charge";
+    case EWALD_ERR_ADMISSION: return "plan workspace exceeds the server's free HBM budget";
     }
     return "unknown status";
 }

@@ -20,6 +20,7 @@ ERR_CAPACITY = -2
 ERR_OUT_OF_MEMORY = -3
 ERR_DEVICE = -4
 ERR_NONFINITE = -5
+ERR_ADMISSION = -6
 
 FP64 = 0
 MIXED = 1
@@ -41,7 +42,23 @@ class Params(ctypes.Structure):
                 ("device", ctypes.c_int32), ("flags", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("n_streams", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("hbm_budget", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("systems", ctypes.c_int64), ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("in_flight", ctypes.c_int64), ("budget", ctypes.c_uint64), ("used", ctypes.c_uint64)]
+
+
 _lib = None
+
+
+def _precision_code(precision) -> int:
+    if isinstance(precision, str):
+        return {"fp64": FP64, "mixed": MIXED}[precision.lower()]
+    return int(precision)
 
 
 def _load():
@@ -89,6 +106,31 @@ def _load():
                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]
     lib.ewald_profile_reset.restype = ctypes.c_int
     lib.ewald_profile_reset.argtypes = [vp]
+    # request server (include/ewald_server.h)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    lib.ewald_server_clock.restype = ctypes.c_double
+    lib.ewald_server_clock.argtypes = []
+    lib.ewald_server_create.restype = ctypes.c_int
+    lib.ewald_server_create.argtypes = [ctypes.POINTER(ServerParams), ctypes.POINTER(vp)]
+    lib.ewald_server_add_system.restype = ctypes.c_int
+    lib.ewald_server_add_system.argtypes = [vp, P, ctypes.POINTER(ctypes.c_int32)]
+    lib.ewald_server_remove_system.restype = ctypes.c_int
+    lib.ewald_server_remove_system.argtypes = [vp, ctypes.c_int32]
+    lib.ewald_server_submit.restype = ctypes.c_int
+    lib.ewald_server_submit.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, vp, vp, vp, vp, vp, i64p]
+    lib.ewald_server_wait.restype = ctypes.c_int
+    lib.ewald_server_wait.argtypes = [vp, ctypes.c_int64, dp, dp]
+    lib.ewald_server_poll.restype = ctypes.c_int
+    lib.ewald_server_poll.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)]
+    lib.ewald_server_drain.restype = ctypes.c_int
+    lib.ewald_server_drain.argtypes = [vp]
+    lib.ewald_server_system_status.restype = ctypes.c_int
+    lib.ewald_server_system_status.argtypes = [vp, ctypes.c_int32]
+    lib.ewald_server_get_stats.restype = ctypes.c_int
+    lib.ewald_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.ewald_server_destroy.restype = None
+    lib.ewald_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -99,8 +141,7 @@ def library():
 
 
 def make_params(n_max, box_L, alpha, r_c, k_max, precision=FP64, device=0, stream=None, flags=0) -> Params:
-    if isinstance(precision, str):
-        precision = {"fp64": FP64, "mixed": MIXED}[precision.lower()]
+    precision = _precision_code(precision)
     return Params(int(n_max), float(box_L), float(alpha), float(r_c), int(k_max), int(precision),
                   int(device), int(flags), stream)
 
@@ -309,3 +350,123 @@ def ewald_energy(pos, q, plan: "Plan"):
     if _EwaldEnergy is None:
         _EwaldEnergy = _autograd_function()
     return _EwaldEnergy.apply(pos, q, plan)
+
+
+class Server:
+    """Request server for many independent systems (``include/ewald_server.h``).
+
+    ``add_system`` registers a system (its plan stays resident); ``submit``
+    enqueues one evaluation and returns a ticket at once; ``wait`` returns the
+    outputs with the submission and completion times on the server clock
+    (``Server.clock()``, the clock of ``time.perf_counter``).  Inputs must be
+    complete on the device when submitted (synchronise their producer first);
+    the binding keeps the tensors of a request alive until it is waited for.
+    """
+
+    def __init__(self, n_streams: int = 4, precision="mixed", device: int = 0, hbm_budget: int = 0):
+        lib = _load()
+        import torch
+        self.device = torch.device("cuda", device)
+        prm = ServerParams(int(device), int(n_streams), _precision_code(precision), 0, int(hbm_budget))
+        h = ctypes.c_void_p()
+        st = lib.ewald_server_create(ctypes.byref(prm), ctypes.byref(h))
+        if st != OK:
+            raise EwaldError(st, "ewald_server_create")
+        self._h = h
+        self._live = {}
+        self._n_max = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(_load().ewald_server_clock())
+
+    @property
+    def handle(self) -> int:
+        if self._h is None:
+            raise RuntimeError("server was destroyed")
+        return self._h.value
+
+    def add_system(self, n_max: int, box_L: float, alpha: float, r_c: float, k_max: int) -> int:
+        prm = make_params(n_max, box_L, alpha, r_c, k_max)
+        sid = ctypes.c_int32(-1)
+        st = _load().ewald_server_add_system(self.handle, ctypes.byref(prm), ctypes.byref(sid))
+        if st != OK:
+            raise EwaldError(st, "ewald_server_add_system")
+        self._n_max[sid.value] = int(n_max)
+        return sid.value
+
+    def remove_system(self, sid: int):
+        st = _load().ewald_server_remove_system(self.handle, int(sid))
+        if st != OK:
+            raise EwaldError(st, "ewald_server_remove_system")
+        self._n_max.pop(sid, None)
+
+    def submit(self, sid: int, pos, q, forces: bool = True, dEdq: bool = False, out=None) -> int:
+        import torch
+        n = int(q.shape[0])
+        for name, t, shape in (("pos", pos, (n, 3)), ("q", q, (n,))):
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        if out is None:
+            e = torch.empty(5, dtype=torch.float64, device=pos.device)
+            f = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if forces else None
+            g = torch.empty(n, dtype=torch.float64, device=pos.device) if dEdq else None
+        else:
+            e, f, g = out
+        t = ctypes.c_int64(-1)
+        st = _load().ewald_server_submit(self.handle, int(sid), n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
+                                         f.data_ptr() if f is not None else None,
+                                         g.data_ptr() if g is not None else None, ctypes.byref(t))
+        if st != OK:
+            raise EwaldError(st, "ewald_server_submit")
+        self._live[t.value] = (pos, q, e, f, g)
+        return t.value
+
+    def wait(self, ticket: int):
+        """((energy, forces, dEdq), t_submit, t_done) of a request."""
+        ts, td = ctypes.c_double(), ctypes.c_double()
+        st = _load().ewald_server_wait(self.handle, int(ticket), ctypes.byref(ts), ctypes.byref(td))
+        live = self._live.pop(ticket, None)
+        if st != OK:
+            raise EwaldError(st, "ewald_server_wait")
+        return live[2:], ts.value, td.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int32(0)
+        st = _load().ewald_server_poll(self.handle, int(ticket), ctypes.byref(done))
+        if st != OK:
+            raise EwaldError(st, "ewald_server_poll")
+        return bool(done.value)
+
+    def drain(self):
+        st = _load().ewald_server_drain(self.handle)
+        if st != OK:
+            raise EwaldError(st, "ewald_server_drain")
+
+    def system_status(self, sid: int) -> int:
+        return int(_load().ewald_server_system_status(self.handle, int(sid)))
+
+    def stats(self) -> Dict[str, int]:
+        out = ServerStats()
+        st = _load().ewald_server_get_stats(self.handle, ctypes.byref(out))
+        if st != OK:
+            raise EwaldError(st, "ewald_server_get_stats")
+        return {k: int(getattr(out, k)) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            _load().ewald_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

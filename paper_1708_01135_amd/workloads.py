@@ -196,9 +196,17 @@ def random_neutral(n: int, box_L: float, seed: int, charge_scale: float = 1.0,
     return pos, q
 
 
+def _serving_system(args):
+    n, density, seed = args
+    # candidate batches sized to the system (the draw order, hence the ions, do
+    # not depend on the batch; only the charge shuffle that follows the draws does)
+    pos, q, _ = electrolyte(n, density, seed, batch=min(65536, max(4096, 2 * n)))
+    return pos, q
+
+
 def serving_mix(n_systems: int = 256, seed: int = 0, n_lo: int = 500, n_hi: int = 50000,
                 density: float = 0.8, r_c: float = 4.5, real_exponent: float = 14.4,
-                rate_hz: float = 1000.0, build_systems: bool = True) -> List[Dict]:
+                rate_hz: float = 1000.0, build_systems: bool = True, workers: int = 1) -> List[Dict]:
     """Independent electrolyte systems for the serving workload.
 
     Sizes: N_s = 2*round(exp(U(ln n_lo, ln n_hi))/2).  Each system is an RSA
@@ -206,6 +214,8 @@ def serving_mix(n_systems: int = 256, seed: int = 0, n_lo: int = 500, n_hi: int 
     alpha * r_c^2 = ``real_exponent`` and K_s = ceil(sqrt(alpha*real_exponent)*L_s/pi)
     matches the reciprocal exponent to the real one.  Arrival times are a
     Poisson process of ``rate_hz`` drawn from ``default_rng(1000 + seed)``.
+    The systems are independent, so ``workers`` > 1 builds them in a process
+    pool (same result).
     """
     rng = np.random.default_rng(seed)
     sizes = 2 * np.round(np.exp(rng.uniform(math.log(n_lo), math.log(n_hi), size=n_systems)) / 2)
@@ -219,12 +229,19 @@ def serving_mix(n_systems: int = 256, seed: int = 0, n_lo: int = 500, n_hi: int 
         n = int(sizes[s])
         L = (n / density) ** (1.0 / 3.0)
         k_max = int(math.ceil(math.sqrt(alpha * real_exponent) * L / math.pi))
-        item = {"n": n, "box_L": L, "alpha": alpha, "r_c": r_c, "k_max": k_max,
-                "t_arrive": float(t_arrive[s]), "seed": seed + 1 + s}
-        if build_systems:
-            pos, q, _ = electrolyte(n, density, seed + 1 + s)
-            item["pos"], item["q"] = pos, q
-        out.append(item)
+        out.append({"n": n, "box_L": L, "alpha": alpha, "r_c": r_c, "k_max": k_max,
+                    "t_arrive": float(t_arrive[s]), "seed": seed + 1 + s})
+    if build_systems:
+        jobs = [(it["n"], density, it["seed"]) for it in out]
+        if workers > 1:
+            import concurrent.futures as cf
+            import multiprocessing as mp
+            with cf.ProcessPoolExecutor(workers, mp_context=mp.get_context("spawn")) as ex:
+                built = list(ex.map(_serving_system, jobs, chunksize=1))
+        else:
+            built = [_serving_system(j) for j in jobs]
+        for it, (pos, q) in zip(out, built):
+            it["pos"], it["q"] = pos, q
     return out
 
 

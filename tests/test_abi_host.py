@@ -1,6 +1,7 @@
 """Host-only checks of the C ABI: the library loads, exports every symbol the
 header declares, and rejects bad arguments before touching a GPU."""
 import ctypes
+import glob
 import os
 import re
 
@@ -13,21 +14,24 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "ewald.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(ewald_\w+)\s*\(", src)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(ewald_\w+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     lib = ew.library()
     names = header_functions()
-    assert len(names) >= 15
+    assert len(names) >= 26
+    assert "ewald_server_submit" in names
     for name in names:
         assert hasattr(lib, name), name
 
 
 def test_status_strings():
-    for st in (0, -1, -2, -3, -4, -5):
+    for st in (0, -1, -2, -3, -4, -5, -6):
         assert ew.status_string(st)
     assert "unknown" in ew.status_string(7)
 
@@ -89,3 +93,37 @@ def test_plan_without_gpu_reports_device_error():
     h = ctypes.c_void_p()
     st = ew.library().ewald_plan(ctypes.byref(p), ctypes.byref(h))
     assert st == ew.ERR_DEVICE and h.value is None
+
+
+@pytest.mark.parametrize("bad", [dict(n_streams=0), dict(n_streams=17), dict(precision=3), dict(flags=1),
+                                 dict(device=-1)])
+def test_server_rejects_bad_parameters_without_gpu(bad):
+    kw = dict(device=0, n_streams=4, precision=ew.MIXED, flags=0, hbm_budget=0)
+    kw.update(bad)
+    prm = ew.ServerParams(kw["device"], kw["n_streams"], kw["precision"], kw["flags"], kw["hbm_budget"])
+    h = ctypes.c_void_p(123)
+    assert ew.library().ewald_server_create(ctypes.byref(prm), ctypes.byref(h)) == ew.ERR_INVALID_ARG
+    assert h.value is None
+
+
+def test_server_null_handling_and_clock():
+    import time
+    lib = ew.library()
+    assert lib.ewald_server_create(None, None) == ew.ERR_INVALID_ARG
+    lib.ewald_server_destroy(None)
+    t = ctypes.c_int64()
+    assert lib.ewald_server_submit(None, 0, 1, 1, 1, 1, None, None, ctypes.byref(t)) == ew.ERR_INVALID_ARG
+    assert lib.ewald_server_wait(None, 0, None, None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_server_drain(None) == ew.ERR_INVALID_ARG
+    # the server clock is CLOCK_MONOTONIC, the clock of time.perf_counter on Linux
+    a = time.perf_counter()
+    c = ew.Server.clock()
+    b = time.perf_counter()
+    assert a - 1e-3 <= c <= b + 1e-3
+
+
+@pytest.mark.skipif(__import__("torch").cuda.is_available(), reason="checks the no-GPU error path")
+def test_server_without_gpu_reports_device_error():
+    prm = ew.ServerParams(0, 4, ew.MIXED, 0, 0)
+    h = ctypes.c_void_p()
+    assert ew.library().ewald_server_create(ctypes.byref(prm), ctypes.byref(h)) == ew.ERR_DEVICE
