@@ -82,7 +82,11 @@ enum {
  *   device     HIP device ordinal the plan lives on.
  *   stream     hipStream_t the work is enqueued on; NULL means the device's
  *              null stream.  May be changed later with ewald_plan_set_stream().
- *   flags      reserved, must be 0. */
+ *   flags      0, or EWALD_FLAG_VALU_GATHER: run the reciprocal force gather on the
+ *              vector ALUs instead of the matrix cores (same results to rounding;
+ *              used to compare the two).  Other bits are invalid.  The matrix-core
+ *              gather also falls back to the vector one when a block's staged z
+ *              powers would exceed 64 KB of LDS (FP64 with k_max > 83). */
 typedef struct {
     int64_t n_max;
     double box_L;
@@ -96,6 +100,7 @@ typedef struct {
 } ewald_params;
 
 #define EWALD_K_MAX_LIMIT 100
+#define EWALD_FLAG_VALU_GATHER 1
 
 /* Static description of a status code (never NULL). */
 const char *ewald_status_string(ewald_status status);

@@ -106,11 +106,41 @@ int sk_tile(int K1);
 hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx, const c64 *ty,
                      const c64 *tz, const int *unit_group, const int *unit_seg, const int *row_nx, const int *row_ny,
                      d4 *part);
+// Matrix-core gather (k_gather_mfma.hip).  The half-space rows are cut, along
+// each n_x line, into quads of kMQuad consecutive n_y; quads sorted by their
+// largest m are grouped kMTileQuads to a tile of 16 rows (the M dimension of a
+// 16x16x4 MFMA).  A tile's coefficients are stored per pair of |n_z| values
+// (a = 2p, 2p+1) as one block of kMBlock values [quantity 4][k 4][row 16]:
+// quantities T_re, T_im, Tz_re, Tz_im; k = (Re z^a, Im z^a, Re z^(a+1),
+// Im z^(a+1)); row = 4 * quad + offset in the quad (FP32), or 4 * offset + quad
+// (FP64, whose MFMA interleaves its output rows over the lane groups).
+constexpr int kMQuad = 4;
+constexpr int kMTileQuads = 4;
+constexpr int kMBlock = 256;
+struct MTile {
+    int base;     // first coefficient block of the tile
+    int nap;      // a pairs (ceil((m_max + 1) / 2))
+    int quad[kMTileQuads];  // n_x << 16 | (n_y of the quad's first row + 32768)
+};
+// sk_reduce writes the VALU gather records to `rec` and, when `mcoef` is
+// given, the same coefficients in the tile layout at row_mbase[row] +
+// (a >> 1) * kMBlock + q * 64 + ((a & 1) * 2 + c) * 16 (c = 0: factor of
+// Re z^a, c = 1: of Im z^a).
 template <typename R>
 hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, const d4 *part,
                             const int *unit_group, const int *unit_seg, const int *row_nx,
                             const int *row_ny, const int *row_m, const int *row_item, const double *ck,
-                            d4 *sk, R *rec, double *erec_part);
+                            d4 *sk, R *rec, R *mcoef, const int *row_mbase, double *erec_part);
+// particles per block of the matrix-core gather (16 per sub-tile)
+template <typename R>
+constexpr int mfma_block_particles()
+{
+    return sizeof(R) == 4 ? 64 : 32;
+}
+size_t gather_mfma_smem_bytes(int nap_max, bool fp64);
+template <typename R>
+hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, int nap_max,
+                              const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart);
 // gather items carry a packed word: segment << 16 | n_x << 8 | (n_y + 128)
 template <typename R>
 hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split,

@@ -1,0 +1,227 @@
+// Reciprocal-space force gather on the matrix cores (section 3.1.2, Algorithm 2,
+// with the per-axis factorisation of Eq. perf_mod1).
+//
+// For particle i and a half-space row (n_x, n_y) the gather needs
+//   T_i  = sum_{n_z} z_i^{n_z} conj(G(n_x, n_y, n_z)),    z_i = exp(i 2 pi z_i / L),
+//   Tz_i = sum_{n_z} n_z z_i^{n_z} conj(G(n_x, n_y, n_z)),
+// and then, with P = exp(i (n_x theta_x + n_y theta_y)),
+//   phi_i += Re(P T),  (F_x, F_y) += (n_x, n_y) Im(P T),  F_z += Im(P Tz).
+// Pairing +-n_z (z^-a = conj z^a) folds each row's sums to a = 0..m with real
+// coefficients on (Re z^a, Im z^a); over all rows and particles that is a real
+// matrix product  [4 quantities x rows] x [2 (m+1)] . [2 (m+1)] x [particles],
+// evaluated here with 16x16x4 MFMAs: rows on M (16 = 4 quads of 4 consecutive
+// n_y at one n_x), particles on N (16 per sub-tile), and two a values per
+// instruction on K.  Coefficients stream from L2, 256 contiguous values per
+// (tile, a pair); the z powers of the block's particles are staged once in
+// LDS.  Lane l owns particle l % 16 of each sub-tile and, in output register
+// r, row 4 (l / 16) + r (FP32) or 4 r + l / 16 (FP64); the plan places quad
+// l / 16's n_y offset r there, so the lane's phases P follow from one FP64
+// sincos and a recurrence along n_y.  Sums over rows are FP64 per lane, then
+// reduced over the four lane groups and the block's waves in a fixed order.
+//
+// FP32 (MIXED): FP32 operands and MFMA accumulation over a, FP32 phases P,
+// FP64 sums over rows.  FP64: every step in double (FP64 MFMA).
+#include "ewald_internal.h"
+
+namespace ewk {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kGmWaves = 4;
+
+template <typename R>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 mma(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+};
+
+template <typename R>
+constexpr int zs_stride()
+{
+    // padded LDS stride of one k component: the four 16-lane groups of a read
+    // start 16 (FP32) or 32 (FP64) banks apart
+    return mfma_block_particles<R>() + 16;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int nap_max,
+                                                                  SplitTable split, const d4 *__restrict__ pq,
+                                                                  const c64 *__restrict__ tz,
+                                                                  const MTile *__restrict__ tiles,
+                                                                  const R *__restrict__ coef, d4 *__restrict__ gpart)
+{
+    using V = typename Mfma<R>::v4;
+    constexpr int NP = mfma_block_particles<R>();
+    constexpr int NSUB = NP / 16;
+    constexpr int ZS = zs_stride<R>();
+    extern __shared__ __align__(16) unsigned char smem[];
+    R *zs = reinterpret_cast<R *>(smem);  // [nap_max][4][ZS]
+
+    const int lane = (int)threadIdx.x & (kLanes - 1);
+    const int w = (int)threadIdx.x / kLanes;
+    const int64_t p0 = (int64_t)blockIdx.x * NP;
+
+    // z powers of the block's particles: entry (p, k, col) = Re/Im z^(2p + k/2)
+    for (int e = (int)threadIdx.x; e < nap_max * 4 * NP; e += kGmWaves * kLanes) {
+        const int col = e % NP, k = (e / NP) & 3, p = e / (4 * NP);
+        int64_t j = p0 + col;
+        j = j < n ? j : n - 1;
+        const c64 z = tz[j * KP + 2 * p + (k >> 1)];
+        zs[(p * 4 + k) * ZS + col] = (R)((k & 1) ? z.im : z.re);
+    }
+
+    const double gk = 2.0 * kPi / L;
+    double thx[NSUB], thy[NSUB];
+    R cy[NSUB], sy[NSUB];
+    double ph[NSUB], fx[NSUB], fy[NSUB], fz[NSUB];
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s) {
+        int64_t j = p0 + 16 * s + (lane & 15);
+        j = j < n ? j : n - 1;
+        const d4 r = pq[j];
+        thx[s] = gk * r.a;
+        thy[s] = gk * r.b;
+        double sn, cs;
+        sincos(thy[s], &sn, &cs);
+        cy[s] = (R)cs;
+        sy[s] = (R)sn;
+        ph[s] = fx[s] = fy[s] = fz[s] = 0.0;
+    }
+    __syncthreads();
+
+    const int g = lane >> 4;  // quad of this lane
+    const int lo = split.lo[blockIdx.y], hi = split.lo[blockIdx.y + 1];
+    const R *zl = zs + g * ZS + (lane & 15);
+    for (int t = lo + w; t < hi; t += kGmWaves) {
+        const MTile tl = tiles[t];
+        V acc[4][NSUB];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int s = 0; s < NSUB; ++s) acc[q][s] = V{0, 0, 0, 0};
+        const R *cb = coef + (size_t)tl.base * kMBlock + lane;
+        R c0 = cb[0], c1 = cb[64], c2 = cb[128], c3 = cb[192];
+        for (int p = 0; p < tl.nap; ++p) {
+            // next pair's coefficients in flight during this pair's MFMAs
+            const R *cn = cb + (size_t)(p + 1 < tl.nap ? p + 1 : p) * kMBlock;
+            const R n0 = cn[0], n1 = cn[64], n2 = cn[128], n3 = cn[192];
+#pragma unroll
+            for (int s = 0; s < NSUB; ++s) {
+                const R z = zl[p * 4 * ZS + 16 * s];
+                acc[0][s] = Mfma<R>::mma(c0, z, acc[0][s]);
+                acc[1][s] = Mfma<R>::mma(c1, z, acc[1][s]);
+                acc[2][s] = Mfma<R>::mma(c2, z, acc[2][s]);
+                acc[3][s] = Mfma<R>::mma(c3, z, acc[3][s]);
+            }
+            c0 = n0;
+            c1 = n1;
+            c2 = n2;
+            c3 = n3;
+        }
+        // epilogue: rows n_y0 + r (r = 0..3) of this lane's quad
+        const int qd = g == 0 ? tl.quad[0] : (g == 1 ? tl.quad[1] : (g == 2 ? tl.quad[2] : tl.quad[3]));
+        const int nx = qd >> 16, ny0 = (qd & 0xffff) - 32768;
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            double sn, cs;
+            sincos((double)nx * thx[s] + (double)ny0 * thy[s], &sn, &cs);
+            R pr = (R)cs, pi = (R)sn;
+            double sim = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const R tr = acc[0][s][r], ti = acc[1][s][r], zr = acc[2][s][r], zi = acc[3][s][r];
+                const R re = pr * tr - pi * ti;   // Re(P T)
+                const R im = pr * ti + pi * tr;   // Im(P T)
+                const R imz = pr * zi + pi * zr;  // Im(P Tz)
+                ph[s] += (double)re;
+                sim += (double)im;
+                fy[s] += (double)(ny0 + r) * (double)im;
+                fz[s] += (double)imz;
+                const R npr = pr * cy[s] - pi * sy[s];
+                pi = pr * sy[s] + pi * cy[s];
+                pr = npr;
+            }
+            fx[s] += (double)nx * sim;
+        }
+    }
+
+    // fixed-order sums: the four lane groups, then the block's waves
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s) {
+#pragma unroll
+        for (int m = 16; m < kLanes; m <<= 1) {
+            ph[s] += __shfl_xor(ph[s], m);
+            fx[s] += __shfl_xor(fx[s], m);
+            fy[s] += __shfl_xor(fy[s], m);
+            fz[s] += __shfl_xor(fz[s], m);
+        }
+    }
+    __syncthreads();  // the z stage is reused for the cross-wave sums
+    d4 *red = reinterpret_cast<d4 *>(smem);  // [kGmWaves][NP]
+    if (lane < 16) {
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            d4 v;
+            v.a = ph[s];
+            v.b = fx[s];
+            v.c = fy[s];
+            v.d = fz[s];
+            red[w * NP + 16 * s + lane] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NP) {
+        const int col = (int)threadIdx.x;
+        d4 o = red[col];
+#pragma unroll
+        for (int u = 1; u < kGmWaves; ++u) {
+            const d4 v = red[u * NP + col];
+            o.a += v.a;
+            o.b += v.b;
+            o.c += v.c;
+            o.d += v.d;
+        }
+        const int64_t j = p0 + col;
+        if (j < n) gpart[(size_t)blockIdx.y * n + j] = o;
+    }
+}
+
+}  // namespace
+
+size_t gather_mfma_smem_bytes(int nap_max, bool fp64)
+{
+    const size_t stage = fp64 ? (size_t)nap_max * 4 * zs_stride<double>() * sizeof(double)
+                              : (size_t)nap_max * 4 * zs_stride<float>() * sizeof(float);
+    const size_t red = (size_t)kGmWaves * (fp64 ? mfma_block_particles<double>() : mfma_block_particles<float>()) *
+                       sizeof(d4);
+    return stage > red ? stage : red;
+}
+
+template <typename R>
+hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, int nap_max,
+                              const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart)
+{
+    const int blocks = ceil_div(a.n, mfma_block_particles<R>());
+    const size_t smem = gather_mfma_smem_bytes(nap_max, sizeof(R) == 8);
+    hipLaunchKernelGGL(k_gather_mfma<R>, dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L, a.KP,
+                       nap_max, split, pq, tz, tiles, mcoef, gpart);
+    return hipGetLastError();
+}
+
+template hipError_t launch_gather_mfma<float>(hipStream_t, const RecipArgs &, int, const SplitTable &, int,
+                                              const d4 *, const c64 *, const MTile *, const float *, d4 *);
+template hipError_t launch_gather_mfma<double>(hipStream_t, const RecipArgs &, int, const SplitTable &, int,
+                                               const d4 *, const c64 *, const MTile *, const double *, d4 *);
+
+}  // namespace ewk

@@ -281,6 +281,7 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
                                                    const int *__restrict__ row_ny, const int *__restrict__ row_m,
                                                    const int *__restrict__ row_item, const double *__restrict__ ck,
                                                    d4 *__restrict__ sk, R *__restrict__ rec,
+                                                   R *__restrict__ mcoef, const int *__restrict__ row_mbase,
                                                    double *__restrict__ erec_part)
 {
     __shared__ double s_e[256];
@@ -335,21 +336,36 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
         out.d = smi;
         sk[slot] = out;
         if (r < n_rows && m >= seg * kQ) {
-            const int item = row_item[seg * n_rows + r];
             // gather coefficients from a = conj(G+), b = conj(G-), G = 2 C S
             const double ar = 2.0 * C * spr, ai = -2.0 * C * spi;
             const double br = 2.0 * C * smr, bi = -2.0 * C * smi;
             const double cu = ar + br, cv = bi - ai, cs = ar - br, ct = ai + bi;
             const double w = (double)a;
-            R *o = rec + ((size_t)item * kQ + k) * 8;
-            o[0] = (R)cu;
-            o[1] = (R)cv;
-            o[2] = (R)cs;
-            o[3] = (R)ct;
-            o[4] = (R)(w * cs);
-            o[5] = (R)(-w * ct);
-            o[6] = (R)(w * cu);
-            o[7] = (R)(-w * cv);
+            if (rec) {
+                const int item = row_item[seg * n_rows + r];
+                R *o = rec + ((size_t)item * kQ + k) * 8;
+                o[0] = (R)cu;
+                o[1] = (R)cv;
+                o[2] = (R)cs;
+                o[3] = (R)ct;
+                o[4] = (R)(w * cs);
+                o[5] = (R)(-w * ct);
+                o[6] = (R)(w * cu);
+                o[7] = (R)(-w * cv);
+            }
+            if (mcoef && a <= m) {
+                // T_re = cu Re z + cv Im z, T_im = ct Re z + cs Im z,
+                // Tz_re = a (cs Re z - ct Im z), Tz_im = a (cu Im z - cv Re z)
+                R *o = mcoef + (size_t)row_mbase[r] + (size_t)(a >> 1) * kMBlock + (size_t)(a & 1) * 32;
+                o[0] = (R)cu;
+                o[16] = (R)cv;
+                o[64] = (R)ct;
+                o[64 + 16] = (R)cs;
+                o[128] = (R)(w * cs);
+                o[128 + 16] = (R)(-w * ct);
+                o[192] = (R)(-w * cv);
+                o[192 + 16] = (R)(w * cu);
+            }
         }
     }
     s_e[threadIdx.x] = e;
@@ -527,11 +543,12 @@ hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_
 template <typename R>
 hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, const d4 *part, const int *unit_group,
                             const int *unit_seg, const int *row_nx, const int *row_ny, const int *row_m,
-                            const int *row_item, const double *ck, d4 *sk, R *rec, double *erec_part)
+                            const int *row_item, const double *ck, d4 *sk, R *rec, R *mcoef, const int *row_mbase,
+                            double *erec_part)
 {
     hipLaunchKernelGGL(k_sk_reduce<R>, dim3(ceil_div(a.n_slots, 256 / kRedLanes)), dim3(256), 0, s, n_chunks, a.n_units,
-                       a.n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec,
-                       erec_part);
+                       a.n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef,
+                       row_mbase, erec_part);
     return hipGetLastError();
 }
 
@@ -549,7 +566,7 @@ hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const S
                                         Cplx<R>::type *, Cplx<R>::type *);                                         \
     template hipError_t launch_sk_reduce<R>(hipStream_t, const RecipArgs &, int, const d4 *, const int *,          \
                                             const int *, const int *, const int *, const int *, const int *,      \
-                                            const double *, d4 *, R *, double *);                                  \
+                                            const double *, d4 *, R *, R *, const int *, double *);               \
     template hipError_t launch_gather<R>(hipStream_t, const RecipArgs &, int, const SplitTable &, const d4 *,      \
                                          const c64 *, const int *, const R *, d4 *);
 

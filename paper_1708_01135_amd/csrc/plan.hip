@@ -24,7 +24,6 @@ constexpr int kMaxCellsPerAxis = 128;
 constexpr int kSkTargetBlocks = 2048;     // structure-factor blocks wanted in flight
 constexpr int kGatherTargetBlocks = 1024; // gather blocks wanted in flight
 constexpr int kMaxChunks = 1024;
-constexpr size_t kSkSmemBudget = 48 * 1024;
 
 // ---------------------------------------------------------- k-set layout
 struct KLayout {
@@ -38,6 +37,11 @@ struct KLayout {
     std::vector<int> item_nx, item_ny, item_seg;
     std::vector<int> item_meta;  // seg << 16 | nx << 8 | (ny + 128)
     std::vector<int> row_item;   // [seg * n_rows + row] -> item, or -1
+    // matrix-core gather: tiles of kMTileQuads quads (kMQuad consecutive n_y at one n_x)
+    std::vector<MTile> mtiles;
+    std::vector<int> row_mbase;      // per (sorted) row: offset of its (tile, row) coefficients
+    std::vector<int64_t> nap_prefix; // prefix sums of the tiles' a pairs
+    int m_blocks = 0, nap_max = 0;
 };
 
 int isqrt_floor(int v)
@@ -48,7 +52,11 @@ int isqrt_floor(int v)
     return r;
 }
 
-void build_klayout(int K, KLayout &kl)
+// fp64_rows: the FP64 16x16x4 MFMA returns row 4 r + g of its output in lane
+// group g, register r (the FP32 one returns row 4 g + r); the tile rows of a
+// quad's n_y offsets follow the instruction the plan will use, so that lane
+// group g always holds quad g.
+void build_klayout(int K, KLayout &kl, bool fp64_rows = false)
 {
     kl.K = K;
     kl.KP = ((K + 1 + kQ - 1) / kQ) * kQ;
@@ -109,6 +117,49 @@ void build_klayout(int K, KLayout &kl)
     kl.item_meta.resize(kl.n_items);
     for (int i = 0; i < kl.n_items; ++i)
         kl.item_meta[i] = (kl.item_seg[i] << 16) | (kl.item_nx[i] << 8) | (kl.item_ny[i] + 128);
+
+    // Matrix-core tiles.  Each n_x line of the natural order (n_y consecutive) is
+    // cut into quads; quads are sorted by their largest m (stable) and grouped
+    // into tiles, the last one padded with empty quads (zero coefficients).
+    struct Quad {
+        int nx, ny0, m;
+        size_t first, count;
+    };
+    std::vector<Quad> quads;
+    for (size_t i = 0; i < nat.size();) {
+        size_t e = i;
+        while (e < nat.size() && nat[e].nx == nat[i].nx) ++e;
+        for (size_t b = i; b < e; b += kMQuad) {
+            Quad q{nat[b].nx, nat[b].ny, -1, b, std::min<size_t>(kMQuad, e - b)};
+            for (size_t u = b; u < b + q.count; ++u) q.m = std::max(q.m, nat[u].m);
+            quads.push_back(q);
+        }
+        i = e;
+    }
+    std::stable_sort(quads.begin(), quads.end(), [](const Quad &a, const Quad &b) { return a.m > b.m; });
+    kl.mtiles.clear();
+    kl.row_mbase.assign(nat.size(), 0);
+    kl.nap_prefix.assign(1, 0);
+    kl.m_blocks = 0;
+    kl.nap_max = 0;
+    for (size_t t0 = 0; t0 < quads.size(); t0 += kMTileQuads) {
+        MTile tl{};
+        tl.base = kl.m_blocks;
+        tl.nap = (quads[t0].m + 2) / 2;  // a = 0 .. m in pairs
+        for (int g = 0; g < kMTileQuads; ++g) {
+            tl.quad[g] = 32768;  // empty quad: n_x = n_y = 0, no coefficients
+            if (t0 + g >= quads.size()) continue;
+            const Quad &q = quads[t0 + g];
+            tl.quad[g] = (q.nx << 16) | (q.ny0 + 32768);
+            for (size_t u = 0; u < q.count; ++u)
+                kl.row_mbase[sorted_of_nat[q.first + u]] =
+                    tl.base * kMBlock + (fp64_rows ? (int)u * kMTileQuads + g : g * kMQuad + (int)u);
+        }
+        kl.m_blocks += tl.nap;
+        kl.nap_max = std::max(kl.nap_max, tl.nap);
+        kl.nap_prefix.push_back(kl.nap_prefix.back() + tl.nap);
+        kl.mtiles.push_back(tl);
+    }
 }
 
 // Cells per axis for the pair loop: side h = L / nc >= r_c / kPairReach.
@@ -139,6 +190,33 @@ int gather_split(int64_t n)
     return (int)std::min<int64_t>(std::max<int64_t>(s, 1), kMaxSplit);
 }
 
+// Row splits (grid.y) of the matrix-core gather: enough blocks to fill the
+// chip, at least two tiles per wave on average; split boundaries balance the
+// tiles' a pairs.
+constexpr int kMfmaTargetBlocks = 1024;
+
+int gather_mfma_split(int64_t n, const KLayout &kl, bool fp64)
+{
+    const int np = fp64 ? mfma_block_particles<double>() : mfma_block_particles<float>();
+    const int64_t blocks = (n + np - 1) / np;
+    int64_t s = (kMfmaTargetBlocks + blocks - 1) / blocks;
+    s = std::min<int64_t>(s, (int64_t)kl.mtiles.size() / 8);
+    return (int)std::min<int64_t>(std::max<int64_t>(s, 1), kMaxSplit);
+}
+
+void mfma_split_table(const KLayout &kl, int n_split, SplitTable &st)
+{
+    const int64_t tot = kl.nap_prefix.back();
+    size_t t = 0;
+    st.lo[0] = 0;
+    for (int k = 1; k < n_split; ++k) {
+        const int64_t want = tot * k / n_split;
+        while (t < kl.mtiles.size() && kl.nap_prefix[t] < want) ++t;
+        st.lo[k] = (int)t;
+    }
+    st.lo[n_split] = (int)kl.mtiles.size();
+}
+
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Sizes of every device buffer; shared by the admission query and the plan.
@@ -148,6 +226,7 @@ struct Sizes {
     size_t tx, part, sk, rec, gpart;
     size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
     size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
+    size_t mcoef, mtiles, row_mbase;
     size_t total;
     int max_chunks;
     int max_pitems;  // pair work items: cells + n/kPairHome bounds sum_c ceil(count_c / kPairHome)
@@ -205,7 +284,10 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.n_pitems = align_up(sizeof(int));
     z.plist = align_up(sizeof(uint32_t) * (size_t)z.list_cap * N);
     z.plist_cnt = align_up(sizeof(int) * N);
-    z.total = 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
+    z.mcoef = align_up(real * (size_t)kl.m_blocks * kMBlock);
+    z.mtiles = align_up(sizeof(MTile) * kl.mtiles.size());
+    z.row_mbase = align_up(sizeof(int) * (size_t)kl.n_rows);
+    z.total = z.mcoef + z.mtiles + z.row_mbase + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
               z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
               3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx;
 }
@@ -237,6 +319,10 @@ struct ewald_plan_s {
         *row_item = nullptr, *item_nx = nullptr, *item_ny = nullptr, *item_seg = nullptr;
     int *pitem_cell = nullptr, *pitem_off = nullptr, *n_pitems = nullptr, *plist_cnt = nullptr;
     uint32_t *plist = nullptr;
+    void *mcoef = nullptr;
+    MTile *mtiles = nullptr;
+    int *row_mbase = nullptr;
+    bool mfma_gather = false;
     // profiling
     bool prof = false;
     std::vector<ProfRec> pending;
@@ -347,7 +433,7 @@ ewald_status ewald_params_validate(const ewald_params *p)
     if (!(std::isfinite(p->r_c) && p->r_c > 0.0 && p->r_c <= p->box_L)) return EWALD_ERR_INVALID_ARG;
     if (p->k_max < 1 || p->k_max > EWALD_K_MAX_LIMIT) return EWALD_ERR_INVALID_ARG;
     if (p->precision != EWALD_PRECISION_FP64 && p->precision != EWALD_PRECISION_MIXED) return EWALD_ERR_INVALID_ARG;
-    if (p->device < 0 || p->flags != 0) return EWALD_ERR_INVALID_ARG;
+    if (p->device < 0 || (p->flags & ~EWALD_FLAG_VALU_GATHER) != 0) return EWALD_ERR_INVALID_ARG;
     return EWALD_OK;
 }
 
@@ -389,7 +475,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->mixed = params->precision == EWALD_PRECISION_MIXED;
     p->nc = cells_per_axis(params->box_L, params->r_c);
     p->ncell = p->nc * p->nc * p->nc;
-    build_klayout(params->k_max, p->kl);
+    build_klayout(params->k_max, p->kl, !p->mixed);
     p->tile = sk_tile(params->k_max + 1);
     compute_sizes(*params, p->kl, p->nc, p->sz);
 
@@ -445,6 +531,12 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->n_pitems = carve<int>(cur, z.n_pitems);
     p->plist = carve<uint32_t>(cur, z.plist);
     p->plist_cnt = carve<int>(cur, z.plist_cnt);
+    p->mcoef = carve<void>(cur, z.mcoef);
+    p->mtiles = carve<MTile>(cur, z.mtiles);
+    p->row_mbase = carve<int>(cur, z.row_mbase);
+    // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
+    p->mfma_gather = !(params->flags & EWALD_FLAG_VALU_GATHER) &&
+                     gather_mfma_smem_bytes(p->kl.nap_max, !p->mixed) <= 64 * 1024;
 
     // C_k by integer |n|^2 (computed once on the host in FP64)
     const int K = params->k_max;
@@ -467,6 +559,10 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (e == hipSuccess) e = upload(p->item_nx, kl.item_nx, s);
     if (e == hipSuccess) e = upload(p->item_ny, kl.item_ny, s);
     if (e == hipSuccess) e = upload(p->item_seg, kl.item_meta, s);
+    if (e == hipSuccess) e = upload(p->mtiles, kl.mtiles, s);
+    if (e == hipSuccess) e = upload(p->row_mbase, kl.row_mbase, s);
+    // padding entries of the tile coefficients are never written and stay zero
+    if (e == hipSuccess) e = hipMemsetAsync(p->mcoef, 0, z.mcoef, s);
     // counters start at zero; afterwards every evaluation leaves them cleared
     if (e == hipSuccess) e = hipMemsetAsync(p->counts, 0, z.counts, s);
     if (e == hipSuccess) e = hipMemsetAsync(p->fill, 0, z.fill, s);
@@ -512,9 +608,12 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     PairArgs pa{n, L, p->nc, p->ncell, p->prm.r_c * p->prm.r_c, p->prm.alpha};
     const int n_chunks = sk_chunks(n, kl.n_units, p->tile);
     const int chunk_len = (int)((n + n_chunks - 1) / n_chunks);
-    const int n_split = gather_split(n);
+    const int n_split = p->mfma_gather ? gather_mfma_split(n, kl, !p->mixed) : gather_split(n);
     SplitTable st{};
-    for (int k = 0; k <= n_split; ++k) st.lo[k] = (int)((int64_t)kl.n_items * k / n_split);
+    if (p->mfma_gather)
+        mfma_split_table(kl, n_split, st);
+    else
+        for (int k = 0; k <= n_split; ++k) st.lo[k] = (int)((int64_t)kl.n_items * k / n_split);
     FinalArgs fa{n, L, p->prm.alpha, energy_only ? 0 : n_split, ceil_div((int64_t)ra.n_slots, 256 / kRedSlotLanes),
                  gscale};
     const int nqb = bin_blocks(n);
@@ -542,24 +641,32 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
                              p->part);
         });
         if (p->mixed) {
+            float *rec = p->mfma_gather ? nullptr : static_cast<float *>(p->rec);
+            float *mc = p->mfma_gather ? static_cast<float *>(p->mcoef) : nullptr;
             run(KC_SKREDUCE, [&] {
                 return launch_sk_reduce<float>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
-                                               p->row_ny, p->row_m, p->row_item, p->ck, p->sk,
-                                               static_cast<float *>(p->rec), p->erec);
+                                               p->row_ny, p->row_m, p->row_item, p->ck, p->sk, rec, mc,
+                                               p->row_mbase, p->erec);
             });
             if (!energy_only) run(KC_GATHER, [&] {
-                return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_seg,
-                                            static_cast<const float *>(p->rec), p->gpart);
+                if (p->mfma_gather)
+                    return launch_gather_mfma<float>(s, ra, n_split, st, kl.nap_max, p->pq, tz, p->mtiles, mc,
+                                                     p->gpart);
+                return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_seg, rec, p->gpart);
             });
         } else {
+            double *rec = p->mfma_gather ? nullptr : static_cast<double *>(p->rec);
+            double *mc = p->mfma_gather ? static_cast<double *>(p->mcoef) : nullptr;
             run(KC_SKREDUCE, [&] {
                 return launch_sk_reduce<double>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
-                                                p->row_ny, p->row_m, p->row_item, p->ck, p->sk,
-                                                static_cast<double *>(p->rec), p->erec);
+                                                p->row_ny, p->row_m, p->row_item, p->ck, p->sk, rec, mc,
+                                                p->row_mbase, p->erec);
             });
             if (!energy_only) run(KC_GATHER, [&] {
-                return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_seg,
-                                             static_cast<const double *>(p->rec), p->gpart);
+                if (p->mfma_gather)
+                    return launch_gather_mfma<double>(s, ra, n_split, st, kl.nap_max, p->pq, tz, p->mtiles, mc,
+                                                      p->gpart);
+                return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_seg, rec, p->gpart);
             });
         }
     }

@@ -25,6 +25,7 @@ ERR_ADMISSION = -6
 FP64 = 0
 MIXED = 1
 K_MAX_LIMIT = 100
+FLAG_VALU_GATHER = 1
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
 
@@ -177,12 +178,12 @@ class Plan:
     """
 
     def __init__(self, n_max: int, box_L: float, alpha: float, r_c: float, k_max: int,
-                 precision="fp64", device: int = 0):
+                 precision="fp64", device: int = 0, flags: int = 0):
         lib = _load()
         import torch
         self.device = torch.device("cuda", device)
         self.params = make_params(n_max, box_L, alpha, r_c, k_max, precision, device,
-                                  _stream_handle(torch.cuda.current_stream(self.device)))
+                                  _stream_handle(torch.cuda.current_stream(self.device)), flags)
         h = ctypes.c_void_p()
         st = lib.ewald_plan(ctypes.byref(self.params), ctypes.byref(h))
         if st != OK:

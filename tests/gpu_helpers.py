@@ -13,7 +13,7 @@ TOL = {
 }
 
 
-def run_gpu(pos, q, L, alpha, rc, K, precision, n_max=None, dEdq=True, plan=None):
+def run_gpu(pos, q, L, alpha, rc, K, precision, n_max=None, dEdq=True, plan=None, flags=0):
     import torch
     from paper_1708_01135_amd import ewald as ew
     dev = torch.device("cuda:0")
@@ -21,7 +21,7 @@ def run_gpu(pos, q, L, alpha, rc, K, precision, n_max=None, dEdq=True, plan=None
     tq = torch.as_tensor(np.ascontiguousarray(q), dtype=torch.float64, device=dev)
     own = plan is None
     if own:
-        plan = ew.Plan(n_max or len(q), L, alpha, rc, K, precision)
+        plan = ew.Plan(n_max or len(q), L, alpha, rc, K, precision, flags=flags)
     try:
         e, f, g = plan.energy_forces(tp, tq, True, dEdq)
         torch.cuda.synchronize()

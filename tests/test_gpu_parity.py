@@ -63,6 +63,28 @@ def test_rocksalt32_full(precision):
             ref(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max), precision, "rocksalt32")
 
 
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("case", SMALL_CASES[1:4] + [("rocksalt32", None, None, None, None, None)],
+                         ids=[c[0] for c in SMALL_CASES[1:4]] + ["rocksalt32"])
+def test_vector_alu_gather_path(case, precision):
+    """The VALU force gather (plan flag) against the oracle, and against the
+    default matrix-core gather on the same inputs."""
+    from paper_1708_01135_amd import ewald as ew
+    if case[0] == "rocksalt32":
+        s = wl.make_config("rocksalt32", 0)
+        pos, q, L, a, rc, K = s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max
+    else:
+        _, n, L, a, rc, K = case
+        pos, q = wl.random_neutral(n, L, seed=n + 1)
+    r_valu = run_gpu(pos, q, L, a, rc, K, precision, flags=ew.FLAG_VALU_GATHER)
+    r_mfma = run_gpu(pos, q, L, a, rc, K, precision)
+    compare(r_valu, ref(pos, q, L, a, rc, K), precision, f"{case[0]}/valu")
+    tol = 1e-12 if precision == "fp64" else 1e-6
+    assert rel_err(r_mfma[1], r_valu[1]) <= tol
+    assert rel_err(r_mfma[2], r_valu[2]) <= tol
+    assert abs(r_mfma[0][0] - r_valu[0][0]) <= tol * abs(r_valu[0][0])
+
+
 def test_madelung_on_gpu():
     for precision, tol in (("fp64", 1e-12), ("mixed", 1e-6)):
         pos, q, L = wl.perfect_rock_salt(8)
