@@ -82,11 +82,14 @@ enum {
  *   device     HIP device ordinal the plan lives on.
  *   stream     hipStream_t the work is enqueued on; NULL means the device's
  *              null stream.  May be changed later with ewald_plan_set_stream().
- *   flags      0, or EWALD_FLAG_VALU_GATHER: run the reciprocal force gather on the
- *              vector ALUs instead of the matrix cores (same results to rounding;
- *              used to compare the two).  Other bits are invalid.  The matrix-core
- *              gather also falls back to the vector one when a block's staged z
- *              powers would exceed 64 KB of LDS (FP64 with k_max > 83). */
+ *   flags      0, or a combination of
+ *                EWALD_FLAG_VALU_GATHER  reciprocal force gather on the vector ALUs,
+ *                EWALD_FLAG_VALU_SK      structure factor on the vector ALUs,
+ *              instead of the matrix cores (same results to rounding; used to
+ *              compare the two).  Other bits are invalid.  The vector kernels are
+ *              also used where the matrix-core ones do not fit: the gather when a
+ *              block's staged z powers would exceed 64 KB of LDS (FP64 with
+ *              k_max > 83), the structure factor for k_max > 47. */
 typedef struct {
     int64_t n_max;
     double box_L;
@@ -101,6 +104,7 @@ typedef struct {
 
 #define EWALD_K_MAX_LIMIT 100
 #define EWALD_FLAG_VALU_GATHER 1
+#define EWALD_FLAG_VALU_SK 2
 
 /* Static description of a status code (never NULL). */
 const char *ewald_status_string(ewald_status status);

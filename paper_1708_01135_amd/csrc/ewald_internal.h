@@ -131,6 +131,18 @@ hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, con
                             const int *unit_group, const int *unit_seg, const int *row_nx,
                             const int *row_ny, const int *row_m, const int *row_item, const double *ck,
                             d4 *sk, R *rec, R *mcoef, const int *row_mbase, double *erec_part);
+// Matrix-core structure factor (k_sk_mfma.hip): one block per (64-row group,
+// particle chunk), one wave per 8-row tile holding up to kSmNat blocks of 8
+// values of a in FP64 MFMA accumulators (k_max <= 8 kSmNat - 1).
+constexpr int kSmWaves = kLanes / 8;
+constexpr int kSmRows = 8;
+constexpr int kSmNat = 6;
+constexpr int kSmStage = 5;  // staged table entries per thread: 3 P KP <= kSmStage * kSmWaves * kLanes
+int sk_mfma_particles(int KP);
+size_t sk_mfma_smem_bytes(int KP);
+hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_groups, int n_chunks, int chunk_len,
+                          const c64 *tx, const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny,
+                          const int *row_m, const int *unit_base, d4 *part);
 // particles per block of the matrix-core gather (16 per sub-tile)
 template <typename R>
 constexpr int mfma_block_particles()

@@ -42,6 +42,7 @@ struct KLayout {
     std::vector<int> row_mbase;      // per (sorted) row: offset of its (tile, row) coefficients
     std::vector<int64_t> nap_prefix; // prefix sums of the tiles' a pairs
     int m_blocks = 0, nap_max = 0;
+    std::vector<int> unit_base;      // first structure-factor unit of each 64-row group
 };
 
 int isqrt_floor(int v)
@@ -101,6 +102,8 @@ void build_klayout(int K, KLayout &kl, bool fp64_rows = false)
         }
     }
     kl.n_units = (int)kl.unit_g.size();
+    kl.unit_base.assign(n_groups, 0);
+    for (int u = kl.n_units - 1; u >= 0; --u) kl.unit_base[kl.unit_g[u]] = u;
     kl.row_item.assign((size_t)kl.n_segmax * kl.n_rows, -1);
     kl.item_nx.clear();
     kl.item_ny.clear();
@@ -194,6 +197,9 @@ int gather_split(int64_t n)
 // chip, at least two tiles per wave on average; split boundaries balance the
 // tiles' a pairs.
 constexpr int kMfmaTargetBlocks = 1024;
+// blocks of kSmWaves waves: two resident per CU (the kernel is built for four
+// waves per SIMD), one round over the 256 CUs
+constexpr int kSkMfmaTargetBlocks = 512;
 
 int gather_mfma_split(int64_t n, const KLayout &kl, bool fp64)
 {
@@ -226,7 +232,7 @@ struct Sizes {
     size_t tx, part, sk, rec, gpart;
     size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
     size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
-    size_t mcoef, mtiles, row_mbase;
+    size_t mcoef, mtiles, row_mbase, unit_base;
     size_t total;
     int max_chunks;
     int max_pitems;  // pair work items: cells + n/kPairHome bounds sum_c ceil(count_c / kPairHome)
@@ -287,7 +293,8 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.mcoef = align_up(real * (size_t)kl.m_blocks * kMBlock);
     z.mtiles = align_up(sizeof(MTile) * kl.mtiles.size());
     z.row_mbase = align_up(sizeof(int) * (size_t)kl.n_rows);
-    z.total = z.mcoef + z.mtiles + z.row_mbase + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
+    z.unit_base = align_up(sizeof(int) * kl.unit_base.size());
+    z.total = z.mcoef + z.mtiles + z.row_mbase + z.unit_base + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
               z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
               3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx;
 }
@@ -322,7 +329,8 @@ struct ewald_plan_s {
     void *mcoef = nullptr;
     MTile *mtiles = nullptr;
     int *row_mbase = nullptr;
-    bool mfma_gather = false;
+    int *unit_base = nullptr;
+    bool mfma_gather = false, mfma_sk = false;
     // profiling
     bool prof = false;
     std::vector<ProfRec> pending;
@@ -433,7 +441,7 @@ ewald_status ewald_params_validate(const ewald_params *p)
     if (!(std::isfinite(p->r_c) && p->r_c > 0.0 && p->r_c <= p->box_L)) return EWALD_ERR_INVALID_ARG;
     if (p->k_max < 1 || p->k_max > EWALD_K_MAX_LIMIT) return EWALD_ERR_INVALID_ARG;
     if (p->precision != EWALD_PRECISION_FP64 && p->precision != EWALD_PRECISION_MIXED) return EWALD_ERR_INVALID_ARG;
-    if (p->device < 0 || (p->flags & ~EWALD_FLAG_VALU_GATHER) != 0) return EWALD_ERR_INVALID_ARG;
+    if (p->device < 0 || (p->flags & ~(EWALD_FLAG_VALU_GATHER | EWALD_FLAG_VALU_SK)) != 0) return EWALD_ERR_INVALID_ARG;
     return EWALD_OK;
 }
 
@@ -534,6 +542,9 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->mcoef = carve<void>(cur, z.mcoef);
     p->mtiles = carve<MTile>(cur, z.mtiles);
     p->row_mbase = carve<int>(cur, z.row_mbase);
+    p->unit_base = carve<int>(cur, z.unit_base);
+    p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmRows * kSmNat &&
+                 sk_mfma_particles(p->kl.KP) >= 8;
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
     p->mfma_gather = !(params->flags & EWALD_FLAG_VALU_GATHER) &&
                      gather_mfma_smem_bytes(p->kl.nap_max, !p->mixed) <= 64 * 1024;
@@ -561,6 +572,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (e == hipSuccess) e = upload(p->item_seg, kl.item_meta, s);
     if (e == hipSuccess) e = upload(p->mtiles, kl.mtiles, s);
     if (e == hipSuccess) e = upload(p->row_mbase, kl.row_mbase, s);
+    if (e == hipSuccess) e = upload(p->unit_base, kl.unit_base, s);
     // padding entries of the tile coefficients are never written and stay zero
     if (e == hipSuccess) e = hipMemsetAsync(p->mcoef, 0, z.mcoef, s);
     // counters start at zero; afterwards every evaluation leaves them cleared
@@ -606,7 +618,16 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     CellArgs ca{n, L, p->nc, p->ncell};
     RecipArgs ra{n, L, kl.K, kl.KP, kl.n_rows, kl.n_units, kl.n_items, kl.n_units * kQ * kLanes};
     PairArgs pa{n, L, p->nc, p->ncell, p->prm.r_c * p->prm.r_c, p->prm.alpha};
-    const int n_chunks = sk_chunks(n, kl.n_units, p->tile);
+    const int n_groups = (int)kl.unit_base.size();
+    int n_chunks = sk_chunks(n, kl.n_units, p->tile);
+    if (p->mfma_sk) {
+        // particle chunks of the matrix-core structure factor: fill the chip, at
+        // most the partial-sum capacity, at least one staged tile per chunk
+        int64_t c = kSkMfmaTargetBlocks / n_groups;
+        c = std::min<int64_t>(c, p->sz.max_chunks);
+        c = std::min<int64_t>(c, (n + sk_mfma_particles(kl.KP) - 1) / sk_mfma_particles(kl.KP));
+        n_chunks = (int)std::max<int64_t>(c, 1);
+    }
     const int chunk_len = (int)((n + n_chunks - 1) / n_chunks);
     const int n_split = p->mfma_gather ? gather_mfma_split(n, kl, !p->mixed) : gather_split(n);
     SplitTable st{};
@@ -637,6 +658,9 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
         auto *tx = static_cast<c64 *>(p->tx), *ty = static_cast<c64 *>(p->ty), *tz = static_cast<c64 *>(p->tz);
         run(KC_PHASE, [&] { return launch_phase<double>(s, ra, p->pq, tx, ty, tz); });
         run(KC_SK, [&] {
+            if (p->mfma_sk)
+                return launch_sk_mfma(s, ra, n_groups, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
+                                      p->row_m, p->unit_base, p->part);
             return launch_sk(s, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
                              p->part);
         });

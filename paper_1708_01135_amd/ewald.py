@@ -26,6 +26,7 @@ FP64 = 0
 MIXED = 1
 K_MAX_LIMIT = 100
 FLAG_VALU_GATHER = 1
+FLAG_VALU_SK = 2
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
 

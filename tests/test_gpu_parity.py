@@ -66,9 +66,9 @@ def test_rocksalt32_full(precision):
 @pytest.mark.parametrize("precision", PRECISIONS)
 @pytest.mark.parametrize("case", SMALL_CASES[1:4] + [("rocksalt32", None, None, None, None, None)],
                          ids=[c[0] for c in SMALL_CASES[1:4]] + ["rocksalt32"])
-def test_vector_alu_gather_path(case, precision):
-    """The VALU force gather (plan flag) against the oracle, and against the
-    default matrix-core gather on the same inputs."""
+def test_vector_alu_reciprocal_paths(case, precision):
+    """The vector-ALU structure factor and force gather (plan flags) against the
+    oracle, and against the default matrix-core kernels on the same inputs."""
     from paper_1708_01135_amd import ewald as ew
     if case[0] == "rocksalt32":
         s = wl.make_config("rocksalt32", 0)
@@ -76,13 +76,17 @@ def test_vector_alu_gather_path(case, precision):
     else:
         _, n, L, a, rc, K = case
         pos, q = wl.random_neutral(n, L, seed=n + 1)
-    r_valu = run_gpu(pos, q, L, a, rc, K, precision, flags=ew.FLAG_VALU_GATHER)
+    r_ref = ref(pos, q, L, a, rc, K)
     r_mfma = run_gpu(pos, q, L, a, rc, K, precision)
-    compare(r_valu, ref(pos, q, L, a, rc, K), precision, f"{case[0]}/valu")
+    compare(r_mfma, r_ref, precision, f"{case[0]}/mfma")
     tol = 1e-12 if precision == "fp64" else 1e-6
-    assert rel_err(r_mfma[1], r_valu[1]) <= tol
-    assert rel_err(r_mfma[2], r_valu[2]) <= tol
-    assert abs(r_mfma[0][0] - r_valu[0][0]) <= tol * abs(r_valu[0][0])
+    for flags, tag in ((ew.FLAG_VALU_GATHER, "valu-gather"), (ew.FLAG_VALU_SK, "valu-sk"),
+                       (ew.FLAG_VALU_GATHER | ew.FLAG_VALU_SK, "valu-both")):
+        r = run_gpu(pos, q, L, a, rc, K, precision, flags=flags)
+        compare(r, r_ref, precision, f"{case[0]}/{tag}")
+        assert rel_err(r_mfma[1], r[1]) <= tol, tag
+        assert rel_err(r_mfma[2], r[2]) <= tol, tag
+        assert abs(r_mfma[0][0] - r[0][0]) <= tol * abs(r[0][0]), tag
 
 
 def test_madelung_on_gpu():
