@@ -35,11 +35,23 @@ WORKLOAD = "rocksalt32"
 # exp(i k.r) conj(G) 6, force accumulate 6, potential 2).  Real space: 30 per
 # ordered pair inside the cutoff (plus three special functions).
 FLOPS_PER_UNIT = {"sk": 10.0, "gather": 20.0}
-# VALU peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for
-# FP64 and for unpacked FP32 (packed dual-FP32 issue is compiled out); the published
-# FP32 vector figure (157.3) counts packed issue and is reported beside it.
+# Peaks (MI355X, dense): the structure factor runs FP64 matrix-core products
+# (78.6 TFLOP/s) in both precisions; the force gather runs FP32 (157.3) or FP64
+# (78.6) matrix-core products.  VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s for FP64 and for unpacked FP32 (packed dual-FP32 issue
+# is compiled out; the published 157.3 FP32 vector figure counts it).
 PEAK_TFLOPS = 78.6
 PEAK_FP32_PUBLISHED = 157.3
+PEAK_MFMA = {"fp64": 78.6, "fp32": 157.3}
+
+
+def kernel_bound(kernel, precision):
+    """(bound, peak TFLOP/s) of a hot kernel in the default (matrix-core) plan."""
+    if kernel == "sk":
+        return "mfma", PEAK_MFMA["fp64"]
+    if kernel == "gather":
+        return "mfma", PEAK_MFMA["fp32" if precision == "mixed" else "fp64"]
+    return "alu", PEAK_TFLOPS
 
 
 def parse():
@@ -61,8 +73,8 @@ def parse():
 
 # Kernel-source files whose hash is stored with the counter-based traffic figures;
 # a changed source invalidates them.
-KERNEL_SOURCES = {"gather": "paper_1708_01135_amd/csrc/k_recip.hip", "sk": "paper_1708_01135_amd/csrc/k_recip.hip",
-                  "pair": "paper_1708_01135_amd/csrc/k_pair.hip"}
+KERNEL_SOURCES = {"gather": "paper_1708_01135_amd/csrc/k_gather_mfma.hip",
+                  "sk": "paper_1708_01135_amd/csrc/k_sk_mfma.hip", "pair": "paper_1708_01135_amd/csrc/k_pair.hip"}
 
 
 def source_hash(kernel):
@@ -281,14 +293,19 @@ def main():
     head_prec = "mixed" if "mixed" in results else "fp64"
     kern = head["kernels"]
     dom = max(("sk", "gather", "pair"), key=lambda k: kern.get(k, {}).get("avg_ms", 0.0))
-    roof = None
-    if dom in FLOPS_PER_UNIT:
-        flops = FLOPS_PER_UNIT[dom] * n * nk
-        ach = flops / (kern[dom]["avg_ms"] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": ach, "peak": PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_TFLOPS, "traffic": traffic_bytes(dom, args.workload, head_prec),
-                "avg_ms": kern[dom]["avg_ms"], "algorithmic_flops_per_launch": flops,
-                "frac_of_published_fp32_peak": ach / PEAK_FP32_PUBLISHED if head_prec == "mixed" else None}
+
+    def roofline(k, prec, kp):
+        if k not in FLOPS_PER_UNIT or k not in kp:
+            return None
+        flops = FLOPS_PER_UNIT[k] * n * nk
+        ach = flops / (kp[k]["avg_ms"] * 1e-3) / 1e12
+        bound, peak = kernel_bound(k, prec)
+        return {"bound": bound, "kernel": k, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+                "traffic": traffic_bytes(k, args.workload, prec), "avg_ms": kp[k]["avg_ms"],
+                "algorithmic_flops_per_launch": flops}
+
+    roof = roofline(dom, head_prec, kern)
+    per_kernel_roofline = {p: {k: roofline(k, p, r["kernels"]) for k in FLOPS_PER_UNIT} for p, r in results.items()}
     serve = None
     if not args.no_serving:
         serve = serving(args.serving_systems, args.serving_passes)
@@ -316,6 +333,7 @@ def main():
         "errors_vs_oracle": errs or None,
         "kernels_ms": {p: {k: round(v["avg_ms"], 5) for k, v in r["kernels"].items()} for p, r in results.items()},
         "roofline": roof,
+        "rooflines_all": per_kernel_roofline,
         "cpu_baseline": cpu,
         "serving": serve,
     }
