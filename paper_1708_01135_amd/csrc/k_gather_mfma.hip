@@ -72,13 +72,30 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     const int w = (int)threadIdx.x / kLanes;
     const int64_t p0 = (int64_t)blockIdx.x * NP;
 
-    // z powers of the block's particles: entry (p, k, col) = Re/Im z^(2p + k/2)
-    for (int e = (int)threadIdx.x; e < nap_max * 4 * NP; e += kGmWaves * kLanes) {
-        const int col = e % NP, k = (e / NP) & 3, p = e / (4 * NP);
-        int64_t j = p0 + col;
-        j = j < n ? j : n - 1;
-        const c64 z = tz[j * KP + 2 * p + (k >> 1)];
-        zs[(p * 4 + k) * ZS + col] = (R)((k & 1) ? z.im : z.re);
+    // z powers of the block's particles: entry (p, k, col) = Re/Im z^(2p + k/2),
+    // loaded eight per thread at a time (indices clamped in bounds, stores
+    // predicated) so that the loads are in flight together
+    constexpr int kBatch = 8;
+    const int total = nap_max * 4 * NP;
+    for (int e0 = (int)threadIdx.x; e0 < total; e0 += kBatch * kGmWaves * kLanes) {
+        double zv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            int e = e0 + u * kGmWaves * kLanes;
+            e = e < total ? e : total - 1;
+            const int col = e % NP, k = (e / NP) & 3, p = e / (4 * NP);
+            int64_t j = p0 + col;
+            j = j < n ? j : n - 1;
+            zv[u] = reinterpret_cast<const double *>(tz + j * KP + 2 * p + (k >> 1))[k & 1];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int e = e0 + u * kGmWaves * kLanes;
+            if (e < total) {
+                const int col = e % NP, k = (e / NP) & 3, p = e / (4 * NP);
+                zs[(p * 4 + k) * ZS + col] = (R)zv[u];
+            }
+        }
     }
 
     const double gk = 2.0 * kPi / L;
