@@ -46,6 +46,40 @@ struct Mfma<double> {
     }
 };
 
+// e^{i theta} rounded to R.  FP64: the library sincos.  FP32: theta is reduced
+// modulo pi/2 in FP64 (Cody-Waite, pi/2 split in two doubles whose first part
+// has 33 significant bits, so k pi/2_hi is exact for |k| < 2^20), the remainder
+// (|r| <= pi/4) is rounded to FP32 and sin, cos are their Taylor series to r^9 and
+// r^10 (truncation below 1e-9 on [-pi/4, pi/4]); the quadrant k mod 4 permutes
+// and signs the pair.  Error about 1 FP32 ulp of the result, as for the rounding
+// of an FP64 value.
+template <typename R>
+__device__ inline void row_phase(double th, R &c, R &s);
+template <>
+__device__ inline void row_phase<double>(double th, double &c, double &s)
+{
+    sincos(th, &s, &c);
+}
+template <>
+__device__ inline void row_phase<float>(double th, float &c, float &s)
+{
+    constexpr double kTwoOverPi = 0.63661977236758134308;
+    constexpr double kPio2Hi = 1.5707963267341256141662597656e+00;  // 33-bit head of pi/2
+    constexpr double kPio2Lo = 6.0771005065061922358e-11;           // pi/2 - kPio2Hi
+    const double k = rint(th * kTwoOverPi);
+    const float r = (float)(fma(-k, kPio2Lo, fma(-k, kPio2Hi, th)));
+    const float r2 = r * r;
+    // sin r = r (1 - r^2/3! + r^4/5! - r^6/7! + r^8/9!), cos r = 1 - r^2/2! + ... + r^8/8! - r^10/10!
+    const float sp = fmaf(fmaf(fmaf(fmaf(2.7557319e-6f, r2, -1.9841270e-4f), r2, 8.3333333e-3f), r2, -1.6666667e-1f), r2, 1.0f);
+    const float cp = fmaf(fmaf(fmaf(fmaf(fmaf(-2.7557319e-7f, r2, 2.4801587e-5f), r2, -1.3888889e-3f), r2, 4.1666667e-2f), r2, -0.5f), r2, 1.0f);
+    const float sr = r * sp;
+    const int q = (int)k & 3;
+    const float a = (q & 1) ? cp : sr;   // sin of theta up to sign
+    const float b = (q & 1) ? sr : cp;   // cos of theta up to sign
+    s = (q & 2) ? -a : a;
+    c = (q == 1 || q == 2) ? -b : b;
+}
+
 template <typename R>
 constexpr int zs_stride()
 {
@@ -69,7 +103,8 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     R *zs = reinterpret_cast<R *>(smem);  // [nap_max][4][ZS]
 
     const int lane = (int)threadIdx.x & (kLanes - 1);
-    const int w = (int)threadIdx.x / kLanes;
+    // wave index made visibly uniform: tile loads and loop control stay scalar
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kLanes);
     const int64_t p0 = (int64_t)blockIdx.x * NP;
 
     // z powers of the block's particles: entry (p, k, col) = Re/Im z^(2p + k/2),
@@ -128,48 +163,70 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
 #pragma unroll
             for (int s = 0; s < NSUB; ++s) acc[q][s] = V{0, 0, 0, 0};
         const R *cb = coef + (size_t)tl.base * kMBlock + lane;
-        R c0 = cb[0], c1 = cb[64], c2 = cb[128], c3 = cb[192];
-        for (int p = 0; p < tl.nap; ++p) {
-            // next pair's coefficients in flight during this pair's MFMAs
-            const R *cn = cb + (size_t)(p + 1 < tl.nap ? p + 1 : p) * kMBlock;
-            const R n0 = cn[0], n1 = cn[64], n2 = cn[128], n3 = cn[192];
+        // operands two a pairs ahead, in three named register sets (the loop is
+        // unrolled by three, so no set is copied and each load has a whole pair
+        // of MFMAs, about 500 cycles, to arrive)
+        auto load_pair = [&](int p, R (&c)[4], R (&z)[NSUB]) {
+            const R *cp = cb + (size_t)p * kMBlock;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) c[q] = cp[64 * q];
+#pragma unroll
+            for (int s = 0; s < NSUB; ++s) z[s] = zl[p * 4 * ZS + 16 * s];
+        };
+        auto mfma_pair = [&](const R (&c)[4], const R (&z)[NSUB]) {
 #pragma unroll
             for (int s = 0; s < NSUB; ++s) {
-                const R z = zl[p * 4 * ZS + 16 * s];
-                acc[0][s] = Mfma<R>::mma(c0, z, acc[0][s]);
-                acc[1][s] = Mfma<R>::mma(c1, z, acc[1][s]);
-                acc[2][s] = Mfma<R>::mma(c2, z, acc[2][s]);
-                acc[3][s] = Mfma<R>::mma(c3, z, acc[3][s]);
+                acc[0][s] = Mfma<R>::mma(c[0], z[s], acc[0][s]);
+                acc[1][s] = Mfma<R>::mma(c[1], z[s], acc[1][s]);
+                acc[2][s] = Mfma<R>::mma(c[2], z[s], acc[2][s]);
+                acc[3][s] = Mfma<R>::mma(c[3], z[s], acc[3][s]);
             }
-            c0 = n0;
-            c1 = n1;
-            c2 = n2;
-            c3 = n3;
+        };
+        const int nap = tl.nap, last = nap - 1;
+        R c0[4], z0[NSUB], c1[4], z1[NSUB], c2[4], z2[NSUB];
+        load_pair(0, c0, z0);
+        load_pair(last < 1 ? last : 1, c1, z1);
+        for (int p = 0; p < nap; p += 3) {
+            load_pair(p + 2 < last ? p + 2 : last, c2, z2);
+            mfma_pair(c0, z0);
+            if (p + 1 < nap) {
+                load_pair(p + 3 < last ? p + 3 : last, c0, z0);
+                mfma_pair(c1, z1);
+            }
+            if (p + 2 < nap) {
+                load_pair(p + 4 < last ? p + 4 : last, c1, z1);
+                mfma_pair(c2, z2);
+            }
         }
-        // epilogue: rows n_y0 + r (r = 0..3) of this lane's quad
+        // epilogue: rows n_y0 + r (r = 0..3) of this lane's quad; the four rows are
+        // summed in R, then added to the FP64 accumulators
         const int qd = g == 0 ? tl.quad[0] : (g == 1 ? tl.quad[1] : (g == 2 ? tl.quad[2] : tl.quad[3]));
         const int nx = qd >> 16, ny0 = (qd & 0xffff) - 32768;
 #pragma unroll
         for (int s = 0; s < NSUB; ++s) {
-            double sn, cs;
-            sincos((double)nx * thx[s] + (double)ny0 * thy[s], &sn, &cs);
-            R pr = (R)cs, pi = (R)sn;
-            double sim = 0.0;
+            R pr, pi;
+            row_phase<R>((double)nx * thx[s] + (double)ny0 * thy[s], pr, pi);
+            R sre = 0, sim = 0, srim = 0, simz = 0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const R tr = acc[0][s][r], ti = acc[1][s][r], zr = acc[2][s][r], zi = acc[3][s][r];
                 const R re = pr * tr - pi * ti;   // Re(P T)
                 const R im = pr * ti + pi * tr;   // Im(P T)
                 const R imz = pr * zi + pi * zr;  // Im(P Tz)
-                ph[s] += (double)re;
-                sim += (double)im;
-                fy[s] += (double)(ny0 + r) * (double)im;
-                fz[s] += (double)imz;
-                const R npr = pr * cy[s] - pi * sy[s];
-                pi = pr * sy[s] + pi * cy[s];
-                pr = npr;
+                sre += re;
+                sim += im;
+                srim += (R)r * im;
+                simz += imz;
+                if (r < 3) {
+                    const R npr = pr * cy[s] - pi * sy[s];
+                    pi = pr * sy[s] + pi * cy[s];
+                    pr = npr;
+                }
             }
-            fx[s] += (double)nx * sim;
+            ph[s] += (double)sre;
+            fx[s] += (double)nx * (double)sim;
+            fy[s] += (double)ny0 * (double)sim + (double)srim;
+            fz[s] += (double)simz;
         }
     }
 
