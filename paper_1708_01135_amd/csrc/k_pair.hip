@@ -227,15 +227,33 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
     const int cnt = act ? list_cnt[i] : 0;
     double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     const uint32_t *mine = list + (size_t)(act ? i : 0) * cap;
-    for (int r = s; __any(r < cnt); r += kSub) {
-        if (r < cnt) {
-            const uint32_t e = mine[r];
-            const int code = (int)(e >> kPairIndexBits);
-            const d4 p = pq[e & ((1u << kPairIndexBits) - 1)];
-            const double dx = (me.a - s_sh[code][0]) - p.a;
-            const double dy = (me.b - s_sh[code][1]) - p.b;
-            const double dz = (me.c - s_sh[code][2]) - p.c;
-            pair_term<MIXED>(dx, dy, dz, dx * dx + dy * dy + dz * dz, p.d, k, ph, fx, fy, fz);
+    // four entries per step: the four list loads, then the four particle loads,
+    // are in flight together (indices clamped inside this particle's list;
+    // entries past the count are loaded but not used)
+    constexpr int kU = 4;
+    const int cnt_l = cnt > 0 ? cnt : 0;
+    for (int r = s; __any(r < cnt_l); r += kU * kSub) {
+        uint32_t e[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int rr = r + u * kSub;
+            e[u] = mine[rr < cap ? rr : cap - 1];
+        }
+        d4 p[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const bool ok = r + u * kSub < cnt_l;
+            p[u] = pq[ok ? (e[u] & ((1u << kPairIndexBits) - 1)) : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (r + u * kSub < cnt_l) {
+                const int code = (int)(e[u] >> kPairIndexBits);
+                const double dx = (me.a - s_sh[code][0]) - p[u].a;
+                const double dy = (me.b - s_sh[code][1]) - p[u].b;
+                const double dz = (me.c - s_sh[code][2]) - p[u].c;
+                pair_term<MIXED>(dx, dy, dz, dx * dx + dy * dy + dz * dz, p[u].d, k, ph, fx, fy, fz);
+            }
         }
     }
     if (__any(cnt < 0)) {
