@@ -29,8 +29,12 @@
  *     Results are returned in the caller's particle order.
  *   - Outputs are overwritten, never accumulated into.
  *   - Calls are stream-ordered and asynchronous on the plan's stream; they
- *     return after enqueueing the work.  Host-detectable errors return before
- *     anything is enqueued.  No call aborts the process.
+ *     return after enqueueing the work.  Internally the reciprocal-space part
+ *     runs on a second stream owned by the plan, forked from and joined back to
+ *     the plan's stream with events, so that it overlaps the real-space part;
+ *     work enqueued on the plan's stream after a call still sees all of that
+ *     call's results and may overwrite its inputs.  Host-detectable errors
+ *     return before anything is enqueued.  No call aborts the process.
  *   - A plan is not re-entrant: calls on one plan must not overlap.  Distinct
  *     plans may be used concurrently on distinct streams.
  *   - Results are bitwise reproducible for identical inputs, plan and device

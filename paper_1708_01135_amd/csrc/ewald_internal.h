@@ -95,9 +95,12 @@ struct RecipArgs {
     int n_items;
     int n_slots;  // n_units * kQ * kLanes
 };
+// Phase tables in caller order from the caller's positions and charges; also
+// writes pr[j] = (wrapped x, y, z, q), the particle records of the reciprocal
+// kernels (which therefore do not wait for the cell list).
 template <typename R>
-hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const d4 *pq, typename Cplx<R>::type *tx,
-                        typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
+hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
+                        typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
 // lanes per slot in the structure-factor reduction (k_sk_reduce)
 constexpr int kRedSlotLanes = 16;
 // structure factor (FP64 phases and sums in both precisions)
@@ -189,6 +192,8 @@ struct FinalArgs {
     int n_erec;
     const double *gscale;  // device scalar g (or null): forces := -g F, dEdq := g dE/dq
 };
+// freal, pq are in cell-sorted order; gpart (reciprocal partial sums) in caller
+// order, read through perm.
 hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
                                      const d4 *freal, const d4 *gpart, const double *scalars,
                                      double *forces, double *dEdq, double *epart);
@@ -197,6 +202,18 @@ hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const doubl
                                   double *energy);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Position reduced into [0, L) (NaN and infinities map to 0; they are flagged
+// separately).  Shared by the cell binning and the phase tables so that both
+// halves of the evaluation see the same wrapped coordinates.
+__device__ inline double wrap_coord(double x, double L)
+{
+    double w = x - L * floor(x / L);
+    if (w < 0.0) w += L;
+    if (w >= L) w -= L;
+    if (!(w >= 0.0 && w < L)) w = 0.0;  // also catches NaN
+    return w;
+}
 
 // MI355X dispatches the workgroups of a launch to its 8 XCDs round-robin by
 // linear block id, and each XCD has its own L2.  Kernels whose neighbouring

@@ -19,15 +19,6 @@ namespace {
 
 constexpr int kBinThreads = 256;
 
-__device__ inline double wrap_coord(double x, double L)
-{
-    double w = x - L * floor(x / L);
-    if (w < 0.0) w += L;
-    if (w >= L) w -= L;
-    if (!(w >= 0.0 && w < L)) w = 0.0;  // also catches NaN
-    return w;
-}
-
 __device__ inline int cell_coord(double w, double L, int nc)
 {
     int c = (int)(w * (double)nc / L);

@@ -1,5 +1,6 @@
 // Totals and output (section 3.2.2 for the self term):
-//   F_i      = F_real,i + q_i (2 pi / L) sum_splits g_i            (caller order)
+//   F_i      = F_real,i + q_i (2 pi / L) sum_splits g_i            (caller order;
+//              the real-space sums are in cell order, the reciprocal ones in caller order)
 //   with an upstream gradient g (device scalar) the outputs become the adjoint
 //   dL/dr_i = -g F_i and dL/dq_i = g dE/dq_i.
 //   dE/dq_i  = phi_real,i + phi_recip,i - 2 sqrt(alpha/pi) q_i - pi Q / (V alpha)
@@ -26,9 +27,10 @@ __global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alp
     double e = 0.0;
     if (s < n) {
         const d4 fr = freal[s];
+        const int64_t i = perm[s];
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
         for (int sp = 0; sp < n_split; ++sp) {
-            const d4 g = gpart[(size_t)sp * n + s];
+            const d4 g = gpart[(size_t)sp * n + i];
             g0 += g.a;
             g1 += g.b;
             g2 += g.c;
@@ -36,7 +38,6 @@ __global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alp
         }
         const double q = pq[s].d;
         const double kf = q * (2.0 * kPi / L);
-        const int64_t i = perm[s];
         const double gs = gscale ? *gscale : 1.0;
         const double fs = gscale ? -gs : 1.0;
         if (forces) {

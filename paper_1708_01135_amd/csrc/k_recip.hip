@@ -46,7 +46,8 @@ __device__ inline typename Cplx<R>::type make_c(double re, double im)
 
 // ------------------------------------------------------------------ k_phase
 template <typename R>
-__global__ __launch_bounds__(256) void k_phase(int64_t n, double L, int KP, const d4 *__restrict__ pq,
+__global__ __launch_bounds__(256) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
+                                               const double *__restrict__ qv, d4 *__restrict__ pr,
                                                typename Cplx<R>::type *__restrict__ tx,
                                                typename Cplx<R>::type *__restrict__ ty,
                                                typename Cplx<R>::type *__restrict__ tz)
@@ -58,21 +59,29 @@ __global__ __launch_bounds__(256) void k_phase(int64_t n, double L, int KP, cons
     const int64_t ja = t / nb;
     const int ax = (int)(ja % 3);
     const int64_t j = ja / 3;
-    const d4 r = pq[j];
-    const double x = ax == 0 ? r.a : (ax == 1 ? r.b : r.c);
+    const double qj = qv[j];
+    const double x = wrap_coord(pos[3 * j + ax], L);
+    if (ax == 0 && b == 0) {
+        d4 r;
+        r.a = x;
+        r.b = wrap_coord(pos[3 * j + 1], L);
+        r.c = wrap_coord(pos[3 * j + 2], L);
+        r.d = qj;
+        pr[j] = r;
+    }
     const double th = (2.0 * kPi / L) * x;
     double s0, c0, sa, ca;
     sincos(th, &s0, &c0);
     sincos((double)(kQ * b) * th, &sa, &ca);
-    const double scale = ax == 0 ? r.d : 1.0;
+    const double scale = ax == 0 ? qj : 1.0;
     typename Cplx<R>::type *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + j * KP + kQ * b;
-    double pr = ca, pi = sa;
+    double pr_ = ca, pi_ = sa;
 #pragma unroll
     for (int k = 0; k < kQ; ++k) {
-        out[k] = make_c<R>(scale * pr, scale * pi);
-        const double nr = pr * c0 - pi * s0;
-        pi = pr * s0 + pi * c0;
-        pr = nr;
+        out[k] = make_c<R>(scale * pr_, scale * pi_);
+        const double nr = pr_ * c0 - pi_ * s0;
+        pi_ = pr_ * s0 + pi_ * c0;
+        pr_ = nr;
     }
 }
 
@@ -502,11 +511,12 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, Spl
 }  // namespace
 
 template <typename R>
-hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const d4 *pq, typename Cplx<R>::type *tx,
-                        typename Cplx<R>::type *ty, typename Cplx<R>::type *tz)
+hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
+                        typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz)
 {
     const int64_t total = a.n * 3 * (a.KP / kQ);
-    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, 256)), dim3(256), 0, s, a.n, a.L, a.KP, pq, tx, ty, tz);
+    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, 256)), dim3(256), 0, s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
+                       tz);
     return hipGetLastError();
 }
 
@@ -562,8 +572,8 @@ hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const S
 }
 
 #define EWK_INSTANTIATE(R)                                                                                         \
-    template hipError_t launch_phase<R>(hipStream_t, const RecipArgs &, const d4 *, Cplx<R>::type *,             \
-                                        Cplx<R>::type *, Cplx<R>::type *);                                         \
+    template hipError_t launch_phase<R>(hipStream_t, const RecipArgs &, const double *, const double *, d4 *,     \
+                                        Cplx<R>::type *, Cplx<R>::type *, Cplx<R>::type *);                        \
     template hipError_t launch_sk_reduce<R>(hipStream_t, const RecipArgs &, int, const d4 *, const int *,          \
                                             const int *, const int *, const int *, const int *, const int *,      \
                                             const double *, d4 *, R *, R *, const int *, double *);               \

@@ -232,7 +232,7 @@ struct Sizes {
     size_t tx, part, sk, rec, gpart;
     size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
     size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
-    size_t mcoef, mtiles, row_mbase, unit_base;
+    size_t mcoef, mtiles, row_mbase, unit_base, pr;
     size_t total;
     int max_chunks;
     int max_pitems;  // pair work items: cells + n/kPairHome bounds sum_c ceil(count_c / kPairHome)
@@ -294,7 +294,8 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.mtiles = align_up(sizeof(MTile) * kl.mtiles.size());
     z.row_mbase = align_up(sizeof(int) * (size_t)kl.n_rows);
     z.unit_base = align_up(sizeof(int) * kl.unit_base.size());
-    z.total = z.mcoef + z.mtiles + z.row_mbase + z.unit_base + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
+    z.pr = align_up(sizeof(d4) * N);
+    z.total = z.pr + z.mcoef + z.mtiles + z.row_mbase + z.unit_base + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
               z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
               3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx;
 }
@@ -309,6 +310,10 @@ struct ProfRec {
 struct ewald_plan_s {
     ewald_params prm{};
     hipStream_t stream = nullptr;
+    // the reciprocal-space kernels run on a plan-owned stream, forked from and
+    // joined back to the caller's stream, concurrently with the real-space ones
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     int device = 0;
     bool mixed = false;
     int nc = 1, ncell = 1;
@@ -330,6 +335,7 @@ struct ewald_plan_s {
     MTile *mtiles = nullptr;
     int *row_mbase = nullptr;
     int *unit_base = nullptr;
+    d4 *pr = nullptr;  // caller-order particle records of the reciprocal kernels
     bool mfma_gather = false, mfma_sk = false;
     // profiling
     bool prof = false;
@@ -372,15 +378,15 @@ hipEvent_t take_event(ewald_plan_s *p)
     return e;
 }
 
-// Runs one launcher, bracketed by events when profiling is on.
+// Runs one launcher on stream s, bracketed by events when profiling is on.
 template <typename F>
-hipError_t timed(ewald_plan_s *p, int kind, F &&launch)
+hipError_t timed(ewald_plan_s *p, hipStream_t s, int kind, F &&launch)
 {
     if (!p->prof) return launch();
     ProfRec r{kind, take_event(p), take_event(p)};
-    if (r.a) (void)hipEventRecord(r.a, p->stream);
+    if (r.a) (void)hipEventRecord(r.a, s);
     hipError_t e = launch();
-    if (r.b) (void)hipEventRecord(r.b, p->stream);
+    if (r.b) (void)hipEventRecord(r.b, s);
     if (r.a && r.b) p->pending.push_back(r);
     return e;
 }
@@ -502,6 +508,16 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
         delete p;
         return EWALD_ERR_OUT_OF_MEMORY;
     }
+    if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+        if (p->aux) (void)hipStreamDestroy(p->aux);
+        (void)hipFree(p->base);
+        delete p;
+        return EWALD_ERR_DEVICE;
+    }
     char *cur = static_cast<char *>(p->base);
     const Sizes &z = p->sz;
     p->cell_of = carve<int>(cur, z.cell_of);
@@ -543,6 +559,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->mtiles = carve<MTile>(cur, z.mtiles);
     p->row_mbase = carve<int>(cur, z.row_mbase);
     p->unit_base = carve<int>(cur, z.unit_base);
+    p->pr = carve<d4>(cur, z.pr);
     p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmRows * kSmNat &&
                  sk_mfma_particles(p->kl.KP) >= 8;
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
@@ -583,6 +600,9 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
+        (void)hipEventDestroy(p->ev_fork);
+        (void)hipEventDestroy(p->ev_join);
+        (void)hipStreamDestroy(p->aux);
         (void)hipFree(p->base);
         delete p;
         return EWALD_ERR_DEVICE;
@@ -640,73 +660,84 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     const int nqb = bin_blocks(n);
 
     hipError_t e = hipSuccess;
-    auto run = [&](int kind, auto &&fn) {
-        if (e == hipSuccess) e = timed(p, kind, fn);
+    auto run = [&](hipStream_t st, int kind, auto &&fn) {
+        if (e == hipSuccess) e = timed(p, st, kind, fn);
     };
-    run(KC_BIN, [&] { return launch_bin(s, ca, pos, q, p->cell_of, p->counts, p->qpart, p->status); });
-    run(KC_SCAN, [&] {
-        return launch_scan(s, ca, p->counts, p->fill, p->cell_start, p->qpart, nqb, p->scalars, p->pitem_cell,
-                           p->pitem_off, p->n_pitems);
-    });
-    run(KC_SCATTER, [&] { return launch_scatter(s, ca, p->cell_of, p->cell_start, p->fill, p->tmp_idx); });
-    run(KC_CELLSORT, [&] { return launch_cellsort(s, ca, p->cell_start, p->tmp_idx, pos, q, p->perm, p->pq); });
-    // Phase tables and the structure factor are FP64 in both precisions (FP32
-    // phase rounding leaves ~1e-5 relative error in S_k of near-lattice systems
-    // at small k); the mixed path rounds phases and coefficients to FP32 in the
-    // gather and evaluates the pair functions in FP32.
+    // Reciprocal space on the plan's own stream, from the caller's positions and
+    // charges: it needs nothing from the cell list, so it runs beside the real
+    // space.  Phase tables and the structure factor are FP64 in both precisions
+    // (FP32 phase rounding leaves ~1e-5 relative error in S_k of near-lattice
+    // systems at small k); the mixed path rounds phases and coefficients to
+    // FP32 in the gather and evaluates the pair functions in FP32.
+    hipStream_t ax = p->aux;
+    if (e == hipSuccess) e = hipEventRecord(p->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ax, p->ev_fork, 0);
     {
         auto *tx = static_cast<c64 *>(p->tx), *ty = static_cast<c64 *>(p->ty), *tz = static_cast<c64 *>(p->tz);
-        run(KC_PHASE, [&] { return launch_phase<double>(s, ra, p->pq, tx, ty, tz); });
-        run(KC_SK, [&] {
+        run(ax, KC_PHASE, [&] { return launch_phase<double>(ax, ra, pos, q, p->pr, tx, ty, tz); });
+        run(ax, KC_SK, [&] {
             if (p->mfma_sk)
-                return launch_sk_mfma(s, ra, n_groups, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
+                return launch_sk_mfma(ax, ra, n_groups, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
                                       p->row_m, p->unit_base, p->part);
-            return launch_sk(s, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
+            return launch_sk(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
                              p->part);
         });
         if (p->mixed) {
             float *rec = p->mfma_gather ? nullptr : static_cast<float *>(p->rec);
             float *mc = p->mfma_gather ? static_cast<float *>(p->mcoef) : nullptr;
-            run(KC_SKREDUCE, [&] {
-                return launch_sk_reduce<float>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
+            run(ax, KC_SKREDUCE, [&] {
+                return launch_sk_reduce<float>(ax, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
                                                p->row_ny, p->row_m, p->row_item, p->ck, p->sk, rec, mc,
                                                p->row_mbase, p->erec);
             });
-            if (!energy_only) run(KC_GATHER, [&] {
+            if (!energy_only) run(ax, KC_GATHER, [&] {
                 if (p->mfma_gather)
-                    return launch_gather_mfma<float>(s, ra, n_split, st, kl.nap_max, p->pq, tz, p->mtiles, mc,
+                    return launch_gather_mfma<float>(ax, ra, n_split, st, kl.nap_max, p->pr, tz, p->mtiles, mc,
                                                      p->gpart);
-                return launch_gather<float>(s, ra, n_split, st, p->pq, tz, p->item_seg, rec, p->gpart);
+                return launch_gather<float>(ax, ra, n_split, st, p->pr, tz, p->item_seg, rec, p->gpart);
             });
         } else {
             double *rec = p->mfma_gather ? nullptr : static_cast<double *>(p->rec);
             double *mc = p->mfma_gather ? static_cast<double *>(p->mcoef) : nullptr;
-            run(KC_SKREDUCE, [&] {
-                return launch_sk_reduce<double>(s, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
+            run(ax, KC_SKREDUCE, [&] {
+                return launch_sk_reduce<double>(ax, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
                                                 p->row_ny, p->row_m, p->row_item, p->ck, p->sk, rec, mc,
                                                 p->row_mbase, p->erec);
             });
-            if (!energy_only) run(KC_GATHER, [&] {
+            if (!energy_only) run(ax, KC_GATHER, [&] {
                 if (p->mfma_gather)
-                    return launch_gather_mfma<double>(s, ra, n_split, st, kl.nap_max, p->pq, tz, p->mtiles, mc,
+                    return launch_gather_mfma<double>(ax, ra, n_split, st, kl.nap_max, p->pr, tz, p->mtiles, mc,
                                                       p->gpart);
-                return launch_gather<double>(s, ra, n_split, st, p->pq, tz, p->item_seg, rec, p->gpart);
+                return launch_gather<double>(ax, ra, n_split, st, p->pr, tz, p->item_seg, rec, p->gpart);
             });
         }
     }
+    if (e == hipSuccess) e = hipEventRecord(p->ev_join, ax);
+
+    // Real space on the caller's stream.
+    run(s, KC_BIN, [&] { return launch_bin(s, ca, pos, q, p->cell_of, p->counts, p->qpart, p->status); });
+    run(s, KC_SCAN, [&] {
+        return launch_scan(s, ca, p->counts, p->fill, p->cell_start, p->qpart, nqb, p->scalars, p->pitem_cell,
+                           p->pitem_off, p->n_pitems);
+    });
+    run(s, KC_SCATTER, [&] { return launch_scatter(s, ca, p->cell_of, p->cell_start, p->fill, p->tmp_idx); });
+    run(s, KC_CELLSORT, [&] { return launch_cellsort(s, ca, p->cell_start, p->tmp_idx, pos, q, p->perm, p->pq); });
     const int max_pitems = p->ncell + ceil_div(n, kPairHome);
-    run(KC_PAIRLIST, [&] {
+    run(s, KC_PAIRLIST, [&] {
         return launch_pair_list(s, pa, max_pitems, p->n_pitems, p->pitem_cell, p->pitem_off, p->cell_start, p->pq,
                                 p->plist, p->plist_cnt, p->sz.list_cap);
     });
-    run(KC_PAIR, [&] {
+    run(s, KC_PAIR, [&] {
         return launch_pair(s, pa, p->mixed, p->cell_start, p->pq, p->plist, p->plist_cnt, p->sz.list_cap, p->freal);
     });
-    run(KC_FINAL_P, [&] {
+
+    // Join, then the totals.
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
+    run(s, KC_FINAL_P, [&] {
         return launch_finalize_particles(s, fa, p->pq, p->perm, p->freal, p->gpart, p->scalars, forces, dEdq,
                                          p->epart);
     });
-    run(KC_FINAL_E, [&] {
+    run(s, KC_FINAL_E, [&] {
         return launch_finalize_energy(s, fa, p->epart, ceil_div(n, 256), p->erec, p->scalars, p->status, energy);
     });
     if (e != hipSuccess) {
@@ -765,6 +796,10 @@ void ewald_release(ewald_plan_t p)
     {
         DeviceGuard dg(p->device);
         (void)hipStreamSynchronize(p->stream);
+        (void)hipStreamSynchronize(p->aux);
+        (void)hipEventDestroy(p->ev_fork);
+        (void)hipEventDestroy(p->ev_join);
+        (void)hipStreamDestroy(p->aux);
         for (const ProfRec &r : p->pending) {
             (void)hipEventDestroy(r.a);
             (void)hipEventDestroy(r.b);
