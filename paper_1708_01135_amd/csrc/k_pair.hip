@@ -11,11 +11,11 @@
 // nc where one cell appears under several shifts.
 //
 // Work item = up to kPairHome (8) home particles of one cell; two passes:
-//  1. k_pair_list: lanes hold 64 candidates at a time (one z-column of five
-//     neighbour cells, read coalesced), the 8 home particles are wave-uniform.
-//     For each home particle the in-range lanes are compacted with a ballot and
-//     appended, in lane order, to that particle's list of 16-bit entries
-//     (neighbour offset code << 9 | index inside that neighbour cell).
+//  1. k_pair_list: the 125 neighbour ranges form one candidate stream, taken
+//     64 at a time (one candidate per lane); the 8 home particles are
+//     wave-uniform.  For each home particle the in-range lanes are compacted
+//     with a ballot and appended, in lane order, to that particle's list of
+//     32-bit entries (sorted index | image-shift code << 25).
 //  2. k_pair: 8 lanes per home particle walk its list (lane s takes entries
 //     s, s+8, ...), so erfc/exp run only for pairs inside r_c; the 8 partial
 //     sums are combined by a fixed xor-shuffle tree.
@@ -102,13 +102,11 @@ __device__ inline int neighbour(int nc, double L, int cx, int cy, int cz, int o,
 }
 
 
-// image-shift code of a stencil offset: base-kSpan digits of the per-axis shift
-// multiples (each in [-kPairReach, kPairReach]) -- shift = (code digits - R) * L
-__device__ inline int shift_code(double sx, double sy, double sz, double L)
+// Cell index and wrap count along one axis: v = w nc + cell, w = floor(v / nc).
+__device__ inline int wrap_count(int v, int nc, int &w)
 {
-    const int ix = (int)rint(sx / L) + kPairReach, iy = (int)rint(sy / L) + kPairReach;
-    const int iz = (int)rint(sz / L) + kPairReach;
-    return (ix * kSpan + iy) * kSpan + iz;
+    w = v >= 0 ? v / nc : -((-v + nc - 1) / nc);
+    return v - w * nc;
 }
 
 __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
@@ -117,8 +115,10 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
                                                   const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                                   uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
 {
-    // neighbour ranges of the home cell: start, length, image shift and code
-    __shared__ int s_start[kStencil], s_len[kStencil], s_code[kStencil];
+    // neighbour ranges of the home cell: start, length, image shift and code,
+    // and the exclusive prefix of the lengths (the candidate stream position of
+    // each neighbour range)
+    __shared__ int s_start[kStencil], s_len[kStencil], s_code[kStencil], s_pre[kStencil];
     __shared__ double s_sx[kStencil], s_sy[kStencil], s_sz[kStencil];
     // neighbouring cells share one XCD's L2: remap over the actual item count
     // (known on the device only), so that padding blocks do not pile up on one XCD
@@ -135,14 +135,17 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     const int i0 = cell_start[c] + item_off[it];
     const int nh = (end - i0) < kPairHome ? (end - i0) : kPairHome;  // wave-uniform
     for (int o = lane; o < kStencil; o += kLanes) {
-        double sx, sy, sz;
-        const int cn = neighbour(nc, L, cx, cy, cz, o, sx, sy, sz);
+        int wx, wy, wz;
+        const int vx = wrap_count(cx + o / (kSpan * kSpan) - kPairReach, nc, wx);
+        const int vy = wrap_count(cy + (o / kSpan) % kSpan - kPairReach, nc, wy);
+        const int vz = wrap_count(cz + o % kSpan - kPairReach, nc, wz);
+        const int cn = (vx * nc + vy) * nc + vz;
         s_start[o] = cell_start[cn];
         s_len[o] = cell_start[cn + 1] - s_start[o];
-        s_code[o] = shift_code(sx, sy, sz, L);
-        s_sx[o] = sx;
-        s_sy[o] = sy;
-        s_sz[o] = sz;
+        s_code[o] = ((wx + kPairReach) * kSpan + (wy + kPairReach)) * kSpan + (wz + kPairReach);
+        s_sx[o] = (double)wx * L;
+        s_sy[o] = (double)wy * L;
+        s_sz[o] = (double)wz * L;
     }
     double hx[kPairHome], hy[kPairHome], hz[kPairHome];
     int cnt[kPairHome];
@@ -155,40 +158,58 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
         cnt[h] = 0;
     }
     __syncthreads();
-    for (int col = 0; col < kSpan * kSpan; ++col) {
-        // the kSpan cells of neighbour column col, concatenated
-        int pre[kSpan];
-        int tot = 0;
+    // exclusive prefix of the 125 lengths; lane l keeps those of offsets l and
+    // l + 64 in registers (read back wave-uniformly with readlane)
+    const int l0 = lane < kStencil ? s_len[lane] : 0;
+    const int l1 = lane + kLanes < kStencil ? s_len[lane + kLanes] : 0;
+    int in0 = l0, in1 = l1;
 #pragma unroll
-        for (int t = 0; t < kSpan; ++t) {
-            pre[t] = tot;
-            tot += s_len[col * kSpan + t];
+    for (int d = 1; d < kLanes; d <<= 1) {
+        const int t0 = __shfl_up(in0, d), t1 = __shfl_up(in1, d);
+        if (lane >= d) {
+            in0 += t0;
+            in1 += t1;
         }
-        for (int p0 = 0; p0 < tot; p0 += kLanes) {
-            const int p = p0 + lane;
-            const bool valid = p < tot;
-            int t = 0;
+    }
+    const int tot0 = __shfl(in0, kLanes - 1);
+    const int pre_lo = in0 - l0, pre_hi = tot0 + in1 - l1;
+    const int total = tot0 + __shfl(in1, kLanes - 1);
+    if (lane < kStencil) s_pre[lane] = pre_lo;
+    if (lane + kLanes < kStencil) s_pre[lane + kLanes] = pre_hi;
+    __syncthreads();
+    // One stream of candidates: the neighbour ranges in offset order, 64 at a
+    // time.  Lane l takes candidate P0 + l, in the last offset whose prefix is
+    // <= P0 + l; the offsets that start inside the chunk are walked once per
+    // chunk (wave-uniform), starting from the offset that held the previous
+    // chunk's last candidate.
+    int cur = 0;
+    for (int P0 = 0; P0 < total; P0 += kLanes) {
+        const int p = P0 + lane;
+        const bool valid = p < total;
+        int o = cur;
+        for (int k = cur + 1; k < kStencil; ++k) {
+            const int pk = k < kLanes ? __builtin_amdgcn_readlane(pre_lo, k) : __builtin_amdgcn_readlane(pre_hi, k - kLanes);
+            if (pk >= P0 + kLanes) break;
+            o += p >= pk ? 1 : 0;
+        }
+        cur = __builtin_amdgcn_readlane(o, kLanes - 1);
+        const int j = valid ? s_start[o] + (p - s_pre[o]) : 0;
+        const d4 q = pq[j];
+        const double px = q.a + s_sx[o], py = q.b + s_sy[o], pz = q.c + s_sz[o];
+        const uint32_t entry = (uint32_t)j | ((uint32_t)s_code[o] << kPairIndexBits);
+        const int self = (valid && o == kCenter) ? j : -1;  // the home cell without shift
 #pragma unroll
-            for (int u = 1; u < kSpan; ++u) t += (p >= pre[u]) ? 1 : 0;
-            const int o = col * kSpan + t;
-            const int base = t == 0 ? pre[0] : (t == 1 ? pre[1] : (t == 2 ? pre[2] : (t == 3 ? pre[3] : pre[4])));
-            const int j = valid ? s_start[o] + (p - base) : 0;
-            const d4 q = pq[j];
-            const double px = q.a + s_sx[o], py = q.b + s_sy[o], pz = q.c + s_sz[o];
-            const uint32_t entry = (uint32_t)j | ((uint32_t)s_code[o] << kPairIndexBits);
-#pragma unroll
-            for (int h = 0; h < kPairHome; ++h) {
-                if (h < nh) {
-                    const double dx = hx[h] - px, dy = hy[h] - py, dz = hz[h] - pz;
-                    const double r2 = dx * dx + dy * dy + dz * dz;
-                    const bool in = valid && r2 < rc2 && !(o == kCenter && j == i0 + h);
-                    const uint64_t m = __ballot(in);
-                    int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                                      __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                    pos = pos < cap ? pos : cap - 1;  // an overflowing list is not used
-                    if (in) list[(size_t)(i0 + h) * cap + pos] = entry;
-                    cnt[h] += __popcll(m);
-                }
+        for (int h = 0; h < kPairHome; ++h) {
+            if (h < nh) {
+                const double dx = hx[h] - px, dy = hy[h] - py, dz = hz[h] - pz;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = valid && r2 < rc2 && self != i0 + h;
+                const uint64_t m = __ballot(in);
+                int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+                pos = pos < cap ? pos : cap - 1;  // an overflowing list is not used
+                if (in) list[(size_t)(i0 + h) * cap + pos] = entry;
+                cnt[h] += __popcll(m);
             }
         }
     }
