@@ -140,6 +140,7 @@ hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, con
 constexpr int kSmWaves = kLanes / 8;
 constexpr int kSmRows = 8;
 constexpr int kSmNat = 6;
+constexpr int kSmNatWide = 3;  // the 16-row variant, k_max <= 8 kSmNatWide - 1
 constexpr int kSmStage = 5;  // staged table entries per thread: 3 P KP <= kSmStage * kSmWaves * kLanes
 int sk_mfma_particles(int KP);
 size_t sk_mfma_smem_bytes(int KP);

@@ -185,6 +185,146 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma(int64_t n, int 
     }
 }
 
+// Wide-tile variant for k_max <= 23 (at most three blocks of 8 values of a per
+// row): a wave owns 16 rows and issues two MFMAs per quad and block of a, one
+// with Re U and one with Im U as the A operand, so every lane forms the U of a
+// distinct (row, particle) and every z read feeds two MFMAs -- half the LDS
+// traffic per MFMA of the 8-row tiles.  A block of kSmWaves waves covers two
+// row groups (128 rows).  Output register r of lane l holds row (l / 16) + 4 r
+// of the tile against column ((l % 16) / 2, l % 2): Re U z (re part) and Im U z
+// (im part); with the partner lane l ^ 1 they give S(+a) and S(-a).
+template <int NAT>
+__device__ __forceinline__ void sk_wide_pass(const c64 *__restrict__ st, int per, int KP, int P, int nx, int ay,
+                                             double ysg, int kq, int bofs, int bim, dv4 (&are)[kSmNatWide],
+                                             dv4 (&aim)[kSmNatWide])
+{
+    for (int pq = 0; pq < P; pq += 4) {
+        const int p = pq + kq;
+        const c64 xv = st[p * KP + nx];
+        const c64 yv = st[per + p * KP + ay];
+        const double yi = ysg * yv.im;
+        const double ur = xv.re * yv.re - xv.im * yi;
+        const double ui = xv.re * yi + xv.im * yv.re;
+        const double *zrow = reinterpret_cast<const double *>(st + 2 * per + p * KP + bofs) + bim;
+        double z[NAT];
+#pragma unroll
+        for (int b = 0; b < NAT; ++b) z[b] = zrow[2 * kSmRows * b];
+#pragma unroll
+        for (int b = 0; b < NAT; ++b) {
+            are[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ur, z[b], are[b], 0, 0, 0);
+            aim[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ui, z[b], aim[b], 0, 0, 0);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n, int KP, int P, int n_rows,
+                                                                     int n_rblocks, int n_chunks, int chunk_len,
+                                                                     const c64 *__restrict__ tx,
+                                                                     const c64 *__restrict__ ty,
+                                                                     const c64 *__restrict__ tz,
+                                                                     const int *__restrict__ row_nx,
+                                                                     const int *__restrict__ row_ny,
+                                                                     const int *__restrict__ row_m,
+                                                                     const int *__restrict__ unit_base, int n_slots,
+                                                                     d4 *__restrict__ part)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    c64 *st = reinterpret_cast<c64 *>(smem);  // [3][P][KP]: q x^n, y^n, z^n
+    const int nb = n_rblocks * n_chunks;
+    const int bid = xcd_remap(blockIdx.x, nb);
+    if (bid >= nb) return;  // padding block (uniform over the block)
+    const int chunk = bid / n_rblocks, rblk = bid % n_rblocks;
+    const int64_t j_lo = (int64_t)chunk * chunk_len;
+    const int64_t j_hi = j_lo + chunk_len < n ? j_lo + chunk_len : n;
+
+    const int lane = (int)threadIdx.x & (kLanes - 1);
+    const int w = (int)threadIdx.x / kLanes;
+    const int tile_row0 = rblk * (2 * kLanes) + w * 16;  // first of the wave's 16 rows
+    // A operand: row tile_row0 + lane % 16 (both parts of its U)
+    const int ra = tile_row0 + (lane & 15);
+    const bool ra_ok = ra < n_rows;
+    const int nx = ra_ok ? row_nx[ra] : 0;
+    const int nyv = ra_ok ? row_ny[ra] : 0;
+    const int ay = nyv < 0 ? -nyv : nyv;
+    const double ysg = nyv < 0 ? -1.0 : 1.0;
+    const int bofs = (lane & 15) >> 1, bim = lane & 1;
+    const int kq = lane >> 4;
+    const int nat = tile_row0 < n_rows ? (row_m[tile_row0] + kSmRows) / kSmRows : 0;
+
+    dv4 are[kSmNatWide], aim[kSmNatWide];
+#pragma unroll
+    for (int b = 0; b < kSmNatWide; ++b) are[b] = aim[b] = dv4{0, 0, 0, 0};
+
+    const int per = P * KP;
+    constexpr int kStride = kSmWaves * kLanes;
+    const c64 *sbase[kSmStage];
+    int soff[kSmStage];
+    bool suse[kSmStage];
+#pragma unroll
+    for (int u = 0; u < kSmStage; ++u) {
+        const int e = (int)threadIdx.x + u * kStride;
+        const int tab = e < per ? 0 : (e < 2 * per ? 1 : 2);
+        suse[u] = e < 3 * per;
+        soff[u] = e - tab * per;
+        sbase[u] = tab == 0 ? tx : (tab == 1 ? ty : tz);
+    }
+    c64 v[kSmStage];
+    auto valid_of = [&](int64_t j0) { return (int)((j_hi - j0 < P ? j_hi - j0 : P) * KP); };
+    auto load_stage = [&](int64_t j0) {
+        const int valid = valid_of(j0);
+#pragma unroll
+        for (int u = 0; u < kSmStage; ++u) {
+            const bool ok = suse[u] && soff[u] < valid;
+            v[u] = sbase[u][j0 * KP + (ok ? soff[u] : 0)];
+        }
+    };
+    if (j_lo < j_hi) load_stage(j_lo);
+    for (int64_t j0 = j_lo; j0 < j_hi; j0 += P) {
+        __syncthreads();
+        const int valid = valid_of(j0);
+#pragma unroll
+        for (int u = 0; u < kSmStage; ++u) {
+            if (suse[u]) {
+                const bool ok = soff[u] < valid;
+                c64 t;
+                t.re = ok ? v[u].re : 0.0;
+                t.im = ok ? v[u].im : 0.0;
+                st[threadIdx.x + u * kStride] = t;
+            }
+        }
+        __syncthreads();
+        if (j0 + P < j_hi) load_stage(j0 + P);
+        switch (nat) {  // wave-uniform
+        case 1: sk_wide_pass<1>(st, per, KP, P, nx, ay, ysg, kq, bofs, bim, are, aim); break;
+        case 2: sk_wide_pass<2>(st, per, KP, P, nx, ay, ysg, kq, bofs, bim, are, aim); break;
+        case 3: sk_wide_pass<3>(st, per, KP, P, nx, ay, ysg, kq, bofs, bim, are, aim); break;
+        default: break;
+        }
+    }
+
+    const int g = lane >> 4;
+#pragma unroll
+    for (int b = 0; b < kSmNatWide; ++b) {
+        if (b >= nat) break;
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int r = tile_row0 + g + 4 * h;
+            const double ur = are[b][h];
+            const double ui = __shfl_xor(aim[b][h], 1);  // partner's Im U with the other z part
+            // Re z column: S+re = P1 - P2, S-re = P1 + P2;  Im z column: S+im = P3 + P4, S-im = P4 - P3
+            const double v1 = bim ? ur + ui : ur - ui;
+            const double v2 = bim ? ui - ur : ur + ui;
+            if (r < n_rows) {
+                const int unit = unit_base[r / kLanes] + b;
+                const int slot = (unit * kQ + bofs) * kLanes + (r & (kLanes - 1));
+                double *o = reinterpret_cast<double *>(part + (size_t)chunk * n_slots + slot);
+                o[bim] = v1;
+                o[2 + bim] = v2;
+            }
+        }
+    }
+}
+
 }  // namespace
 
 // Particles per staged sub-chunk: the largest of 32, 16, 8 whose three tables
@@ -204,6 +344,13 @@ hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_groups, int n
                           const int *row_m, const int *unit_base, d4 *part)
 {
     const int P = sk_mfma_particles(a.KP);
+    if (a.KP <= kSmRows * kSmNatWide) {
+        const int n_rblocks = (a.n_rows + 2 * kLanes - 1) / (2 * kLanes);
+        hipLaunchKernelGGL(k_sk_mfma_wide, dim3(xcd_grid(n_rblocks * n_chunks)), dim3(kSmWaves * kLanes),
+                           sk_mfma_smem_bytes(a.KP), s, a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty,
+                           tz, row_nx, row_ny, row_m, unit_base, a.n_slots, part);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_sk_mfma, dim3(xcd_grid(n_groups * n_chunks)), dim3(kSmWaves * kLanes), sk_mfma_smem_bytes(a.KP),
                        s, a.n, a.KP, P, a.n_rows, n_groups, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m,
                        unit_base, a.n_slots, part);

@@ -201,6 +201,20 @@ constexpr int kMfmaTargetBlocks = 1024;
 // waves per SIMD), one round over the 256 CUs
 constexpr int kSkMfmaTargetBlocks = 512;
 
+// Row blocks of the matrix-core structure factor: 128-row blocks for the wide
+// variant (k_max <= 8 kSmNatWide - 1), 64-row groups otherwise.
+int sk_mfma_row_blocks(const KLayout &kl)
+{
+    if (kl.KP <= kSmRows * kSmNatWide) return (kl.n_rows + 2 * kLanes - 1) / (2 * kLanes);
+    return (int)kl.unit_base.size();
+}
+
+// Particle chunks the matrix-core structure factor may use (partial-sum capacity).
+int sk_mfma_chunk_cap(const KLayout &kl)
+{
+    return std::max(1, std::min(kMaxChunks, kSkMfmaTargetBlocks / sk_mfma_row_blocks(kl)));
+}
+
 int gather_mfma_split(int64_t n, const KLayout &kl, bool fp64)
 {
     const int np = fp64 ? mfma_block_particles<double>() : mfma_block_particles<float>();
@@ -258,7 +272,7 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     const size_t creal = sizeof(c64);  // phase tables are FP64 in both precisions
     const size_t real = mixed ? sizeof(float) : sizeof(double);
     const int tile = sk_tile(kl.K + 1);
-    z.max_chunks = sk_chunks(N, kl.n_units, tile);
+    z.max_chunks = std::max(sk_chunks(N, kl.n_units, tile), sk_mfma_chunk_cap(kl));
     const size_t n_slots = (size_t)kl.n_units * kQ * kLanes;
     const size_t gcap = std::min<size_t>((size_t)kMaxSplit * N, (size_t)kGatherTargetBlocks * 256 + N);
     z.cell_of = align_up(sizeof(int) * N);
@@ -643,7 +657,7 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     if (p->mfma_sk) {
         // particle chunks of the matrix-core structure factor: fill the chip, at
         // most the partial-sum capacity, at least one staged tile per chunk
-        int64_t c = kSkMfmaTargetBlocks / n_groups;
+        int64_t c = kSkMfmaTargetBlocks / sk_mfma_row_blocks(kl);
         c = std::min<int64_t>(c, p->sz.max_chunks);
         c = std::min<int64_t>(c, (n + sk_mfma_particles(kl.KP) - 1) / sk_mfma_particles(kl.KP));
         n_chunks = (int)std::max<int64_t>(c, 1);
