@@ -12,9 +12,9 @@
 //
 // Work layout (MI355X-first, VALU-bound; no floating-point atomics):
 //  * k_phase   builds per-particle tables of exp(i n theta_a), n = 0..KP-1, for the
-//              three axes (x table pre-multiplied by q).  Powers come from an FP64
-//              recurrence re-anchored every kQ steps at exp(i kQ m theta) taken from
-//              FP64 sincos, then rounded to the table type.
+//              three axes (x table pre-multiplied by q), in the caller's particle
+//              order.  Powers come from FP64 recurrences: exp(i theta) inside blocks
+//              of kQ, exp(i kQ theta) from block to block, both from FP64 sincos.
 //  * k_sk      one block = one "unit" (64 rows x one segment of kQ values a = |n_z|)
 //              times one particle chunk.  Lanes own rows; the particle loop is
 //              wave-uniform, so exp(i a theta_z) for the segment is read through the
@@ -34,6 +34,7 @@ namespace ewk {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr int kPhaseRows = 64;  // table rows (particle, axis) per phase block
 
 template <typename R>
 __device__ inline typename Cplx<R>::type make_c(double re, double im)
@@ -45,43 +46,69 @@ __device__ inline typename Cplx<R>::type make_c(double re, double im)
 }
 
 // ------------------------------------------------------------------ k_phase
+// One thread per table row (particle j, axis): two FP64 sincos (theta and
+// kQ theta); the powers inside each block of kQ follow the FP64 recurrence from
+// the block's anchor, and the anchors advance by exp(i kQ theta) (at most
+// kQ + KP / kQ rounding steps from an exact value).  The block's rows are
+// staged in LDS and stored with consecutive threads on consecutive entries.
 template <typename R>
-__global__ __launch_bounds__(256) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
-                                               const double *__restrict__ qv, d4 *__restrict__ pr,
-                                               typename Cplx<R>::type *__restrict__ tx,
-                                               typename Cplx<R>::type *__restrict__ ty,
-                                               typename Cplx<R>::type *__restrict__ tz)
+__global__ __launch_bounds__(kPhaseRows) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
+                                                      const double *__restrict__ qv, d4 *__restrict__ pr,
+                                                      typename Cplx<R>::type *__restrict__ tx,
+                                                      typename Cplx<R>::type *__restrict__ ty,
+                                                      typename Cplx<R>::type *__restrict__ tz)
 {
-    const int nb = KP / kQ;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= n * 3 * nb) return;
-    const int b = (int)(t % nb);
-    const int64_t ja = t / nb;
-    const int ax = (int)(ja % 3);
-    const int64_t j = ja / 3;
-    const double qj = qv[j];
-    const double x = wrap_coord(pos[3 * j + ax], L);
-    if (ax == 0 && b == 0) {
-        d4 r;
-        r.a = x;
-        r.b = wrap_coord(pos[3 * j + 1], L);
-        r.c = wrap_coord(pos[3 * j + 2], L);
-        r.d = qj;
-        pr[j] = r;
-    }
-    const double th = (2.0 * kPi / L) * x;
-    double s0, c0, sa, ca;
-    sincos(th, &s0, &c0);
-    sincos((double)(kQ * b) * th, &sa, &ca);
-    const double scale = ax == 0 ? qj : 1.0;
-    typename Cplx<R>::type *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + j * KP + kQ * b;
-    double pr_ = ca, pi_ = sa;
+    using C = typename Cplx<R>::type;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *buf = reinterpret_cast<C *>(smem);  // [rows of the block][KP]
+    const int rows = (int)blockDim.x;
+    const int64_t total = n * 3;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int64_t row = r0 + threadIdx.x;
+    if (row < total) {
+        const int ax = (int)(row % 3);
+        const int64_t j = row / 3;
+        const double qj = qv[j];
+        const double x = wrap_coord(pos[3 * j + ax], L);
+        if (ax == 0) {
+            d4 r;
+            r.a = x;
+            r.b = wrap_coord(pos[3 * j + 1], L);
+            r.c = wrap_coord(pos[3 * j + 2], L);
+            r.d = qj;
+            pr[j] = r;
+        }
+        const double th = (2.0 * kPi / L) * x;
+        double s1, c1, s8, c8;
+        sincos(th, &s1, &c1);
+        sincos((double)kQ * th, &s8, &c8);
+        const double scale = ax == 0 ? qj : 1.0;
+        double ar = scale, ai = 0.0;  // anchor q exp(i kQ b theta)
+        C *dst = buf + (size_t)threadIdx.x * KP;
+        for (int b = 0; b < KP; b += kQ) {
+            double pr_ = ar, pi_ = ai;
 #pragma unroll
-    for (int k = 0; k < kQ; ++k) {
-        out[k] = make_c<R>(scale * pr_, scale * pi_);
-        const double nr = pr_ * c0 - pi_ * s0;
-        pi_ = pr_ * s0 + pi_ * c0;
-        pr_ = nr;
+            for (int k = 0; k < kQ; ++k) {
+                dst[b + k] = make_c<R>(pr_, pi_);
+                const double nr = pr_ * c1 - pi_ * s1;
+                pi_ = pr_ * s1 + pi_ * c1;
+                pr_ = nr;
+            }
+            const double na = ar * c8 - ai * s8;
+            ai = ar * s8 + ai * c8;
+            ar = na;
+        }
+    }
+    __syncthreads();
+    const int64_t nrows = total - r0 < rows ? total - r0 : rows;
+    const int count = (int)nrows * KP;
+    for (int e = (int)threadIdx.x; e < count; e += rows) {
+        const int lr = e / KP, k = e - lr * KP;
+        const int64_t rg = r0 + lr;
+        const int ax = (int)(rg % 3);
+        const int64_t j = rg / 3;
+        C *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + j * KP + k;
+        *out = buf[e];
     }
 }
 
@@ -514,8 +541,12 @@ template <typename R>
 hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
                         typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz)
 {
-    const int64_t total = a.n * 3 * (a.KP / kQ);
-    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, 256)), dim3(256), 0, s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
+    // rows per block: kPhaseRows, fewer when their LDS stage would pass 64 KB
+    int rows = kPhaseRows;
+    while (rows > 1 && (size_t)rows * a.KP * sizeof(typename Cplx<R>::type) > 64 * 1024) rows /= 2;
+    const int64_t total = a.n * 3;
+    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, rows)), dim3(rows),
+                       (size_t)rows * a.KP * sizeof(typename Cplx<R>::type), s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
                        tz);
     return hipGetLastError();
 }
