@@ -11,32 +11,35 @@
 // nc where one cell appears under several shifts.
 //
 // Work item = up to kPairHome (8) home particles of one cell; two passes:
-//  1. k_pair_list: the 125 neighbour ranges form one candidate stream, taken
-//     64 at a time (one candidate per lane); the 8 home particles are
-//     wave-uniform.  For each home particle the in-range lanes are compacted
+//  1. k_pair_list: the non-empty neighbour ranges form one candidate stream,
+//     taken 64 at a time (one candidate per lane, its range found from a bit
+//     map of the range starts); the 8 home particles are wave-uniform.  For each home particle the in-range lanes are compacted
 //     with a ballot and appended, in lane order, to that particle's list of
 //     32-bit entries (sorted index | image-shift code << 25).
 //  2. k_pair: 8 lanes per home particle walk its list (lane s takes entries
 //     s, s+8, ...), so erfc/exp run only for pairs inside r_c; the 8 partial
 //     sums are combined by a fixed xor-shuffle tree.
 // Both passes run in a fixed order, so results are bitwise reproducible.  A home
-// particle whose list would overflow, or whose neighbourhood holds a cell of
-// more than 512 particles, is evaluated by the exact direct loop instead.
+// particle whose list would overflow is evaluated by the exact direct loop
+// instead.
 //
 // Precision: FP64 computes everything in double.  MIXED forms d and |d|^2 in
-// FP64 (exact cutoff test, no cancellation), evaluates erfc/exp/rsqrt in FP32,
-// and accumulates phi and F in FP64.
+// FP64 (exact cutoff test, no cancellation), evaluates the pair terms in FP32
+// (erfc as exp(-x^2) times a polynomial fit of erfc(x) exp(x^2), the Gaussian
+// from the FP64 exponent), and accumulates phi and F in FP64.
 #include "ewald_internal.h"
+#include "erfcx_fit.h"
 
 namespace ewk {
 
 namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kLog2e = 1.44269504088896340735992468100189214;
 
 struct PairConsts {
-    double sa, tsap, alpha;
-    float saf, tsapf, alphaf;
+    double sa, tsap, alpha, nal2;
+    float saf, tsapf;
 };
 
 __device__ inline PairConsts pair_consts(double alpha)
@@ -45,23 +48,47 @@ __device__ inline PairConsts pair_consts(double alpha)
     k.alpha = alpha;
     k.sa = sqrt(alpha);
     k.tsap = 2.0 * sqrt(alpha / kPi);
+    k.nal2 = -alpha * kLog2e;
     k.saf = (float)k.sa;
     k.tsapf = (float)k.tsap;
-    k.alphaf = (float)alpha;
     return k;
+}
+
+// exp(-alpha r^2) in FP32 from the FP64 exponent: 2^a with a = -alpha log2(e) r^2
+// split as n + f, n = rint(a), so the FP32 power of two sees |f| <= 1/2 and the
+// exponent's own FP32 rounding does not grow with alpha r^2.
+__device__ inline float gauss_f32(double r2, const PairConsts &k)
+{
+    const double a = k.nal2 * r2;
+    const double n = __builtin_rint(a);
+    return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((float)(a - n)), (int)n);
+}
+
+// erfc(x) exp(x^2) for x >= 0 in FP32 (polynomial in t = 1 / (1 + x / 2),
+// coefficients in erfcx_fit.h).
+__device__ inline float erfcx_f32(float x)
+{
+    const float t = __builtin_amdgcn_rcpf(1.0f + kErfcxT * x);
+    float acc = kErfcxP[kErfcxDegree];
+#pragma unroll
+    for (int i = kErfcxDegree - 1; i >= 0; --i) acc = __builtin_fmaf(acc, t, kErfcxP[i]);
+    return acc * t;
 }
 
 // One pair inside the cutoff: accumulate phi += q_j erfc(sa r)/r and
 // F += q_j [erfc(sa r)/r + 2 sqrt(a/pi) exp(-a r^2)] / r^2 * d (q_i applied later).
+// MIXED writes erfc(sa r) = exp(-a r^2) erfcx(sa r), so the one Gaussian serves
+// both terms.
 template <bool MIXED>
 __device__ inline void pair_term(double dx, double dy, double dz, double r2, double qj, const PairConsts &k,
                                  double &ph, double &fx, double &fy, double &fz)
 {
     if constexpr (MIXED) {
         const float r2f = (float)r2;
-        const float ri = rsqrtf(r2f);
-        const float ec = erfcf(k.saf * (r2f * ri)) * ri;
-        const float gg = k.tsapf * expf(-k.alphaf * r2f);
+        const float ri = __builtin_amdgcn_rsqf(r2f);
+        const float e = gauss_f32(r2, k);
+        const float ec = e * erfcx_f32(k.saf * (r2f * ri)) * ri;
+        const float gg = k.tsapf * e;
         const float qf = (float)qj;
         const double f = (double)(qf * (ec + gg) * (ri * ri));
         ph += (double)(qf * ec);
@@ -109,17 +136,22 @@ __device__ inline int wrap_count(int v, int nc, int &w)
     return v - w * nc;
 }
 
+// Stream positions covered by one start-bit map (the map is rebuilt for every
+// further kStreamSeg candidates of a larger neighbourhood).
+constexpr int kStreamSeg = 2048;
+
 __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
                                                   const int *__restrict__ n_items,
                                                   const int *__restrict__ item_cell, const int *__restrict__ item_off,
                                                   const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                                   uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
 {
-    // neighbour ranges of the home cell: start, length, image shift and code,
-    // and the exclusive prefix of the lengths (the candidate stream position of
-    // each neighbour range)
-    __shared__ int s_start[kStencil], s_len[kStencil], s_code[kStencil], s_pre[kStencil];
+    // the non-empty neighbour ranges of the home cell, in offset order: start,
+    // stream position (exclusive prefix of the lengths), image-shift code and
+    // shift; and a bit map of the stream positions at which a range starts
+    __shared__ int s_start[kStencil], s_pre[kStencil], s_code[kStencil];
     __shared__ double s_sx[kStencil], s_sy[kStencil], s_sz[kStencil];
+    __shared__ uint64_t s_bits[kStreamSeg / 64];
     // neighbouring cells share one XCD's L2: remap over the actual item count
     // (known on the device only), so that padding blocks do not pile up on one XCD
     const int nit = *n_items;
@@ -134,19 +166,59 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     const int end = cell_start[c + 1];
     const int i0 = cell_start[c] + item_off[it];
     const int nh = (end - i0) < kPairHome ? (end - i0) : kPairHome;  // wave-uniform
-    for (int o = lane; o < kStencil; o += kLanes) {
-        int wx, wy, wz;
-        const int vx = wrap_count(cx + o / (kSpan * kSpan) - kPairReach, nc, wx);
-        const int vy = wrap_count(cy + (o / kSpan) % kSpan - kPairReach, nc, wy);
-        const int vz = wrap_count(cz + o % kSpan - kPairReach, nc, wz);
-        const int cn = (vx * nc + vy) * nc + vz;
-        s_start[o] = cell_start[cn];
-        s_len[o] = cell_start[cn + 1] - s_start[o];
-        s_code[o] = ((wx + kPairReach) * kSpan + (wy + kPairReach)) * kSpan + (wz + kPairReach);
-        s_sx[o] = (double)wx * L;
-        s_sy[o] = (double)wy * L;
-        s_sz[o] = (double)wz * L;
+    // lane l takes offsets l and l + 64
+    int st[2], len[2], code[2], wxyz[2][3];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int o = lane + u * kLanes;
+        len[u] = 0;
+        st[u] = 0;
+        code[u] = 0;
+        if (o < kStencil) {
+            const int vx = wrap_count(cx + o / (kSpan * kSpan) - kPairReach, nc, wxyz[u][0]);
+            const int vy = wrap_count(cy + (o / kSpan) % kSpan - kPairReach, nc, wxyz[u][1]);
+            const int vz = wrap_count(cz + o % kSpan - kPairReach, nc, wxyz[u][2]);
+            const int cn = (vx * nc + vy) * nc + vz;
+            st[u] = cell_start[cn];
+            len[u] = cell_start[cn + 1] - st[u];
+            code[u] = ((wxyz[u][0] + kPairReach) * kSpan + (wxyz[u][1] + kPairReach)) * kSpan +
+                      (wxyz[u][2] + kPairReach);
+        }
     }
+    // stream positions: inclusive scans of the two halves' lengths
+    int in0 = len[0], in1 = len[1];
+#pragma unroll
+    for (int d = 1; d < kLanes; d <<= 1) {
+        const int t0 = __shfl_up(in0, d), t1 = __shfl_up(in1, d);
+        if (lane >= d) {
+            in0 += t0;
+            in1 += t1;
+        }
+    }
+    const int tot0 = __builtin_amdgcn_readlane(in0, kLanes - 1);
+    const int total = tot0 + __builtin_amdgcn_readlane(in1, kLanes - 1);  // wave-uniform
+    const int pre[2] = {in0 - len[0], tot0 + in1 - len[1]};
+    // ordinals of the non-empty ranges
+    const uint64_t ne0 = __builtin_amdgcn_ballot_w64(len[0] > 0);
+    const uint64_t ne1 = __builtin_amdgcn_ballot_w64(len[1] > 0);
+    const int mb0 = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(ne0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ne0, 0u));
+    const int mb1 = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(ne1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)ne1, 0u));
+    const int ordv[2] = {mb0, (int)__popcll(ne0) + mb1};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (len[u] > 0) {
+            const int k = ordv[u];
+            s_start[k] = st[u];
+            s_pre[k] = pre[u];
+            s_code[k] = code[u];
+            s_sx[k] = (double)wxyz[u][0] * L;
+            s_sy[k] = (double)wxyz[u][1] * L;
+            s_sz[k] = (double)wxyz[u][2] * L;
+        }
+    }
+    // ordinal of the home cell's own range without shift (never empty: it
+    // holds the home particles)
+    const int self_ord = __builtin_amdgcn_readlane(ordv[kCenter / kLanes], kCenter % kLanes);
     double hx[kPairHome], hy[kPairHome], hz[kPairHome];
     int cnt[kPairHome];
 #pragma unroll
@@ -157,59 +229,58 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
         hz[h] = p.c;
         cnt[h] = 0;
     }
-    __syncthreads();
-    // exclusive prefix of the 125 lengths; lane l keeps those of offsets l and
-    // l + 64 in registers (read back wave-uniformly with readlane)
-    const int l0 = lane < kStencil ? s_len[lane] : 0;
-    const int l1 = lane + kLanes < kStencil ? s_len[lane + kLanes] : 0;
-    int in0 = l0, in1 = l1;
+    // One stream of candidates: the non-empty ranges in offset order, 64 at a
+    // time (lane l takes position P0 + l).  Lane l's range is the last one
+    // starting at or before its position: its ordinal is the number of range
+    // starts in [0, P0 + l], minus one, read off the start-bit map.
+    int base = 0;  // range starts before the current chunk
+    for (int seg = 0; seg < total; seg += kStreamSeg) {
+        __syncthreads();  // the previous segment's map is no longer read
+        for (int w = lane; w < kStreamSeg / 64; w += kLanes) s_bits[w] = 0;
+        __syncthreads();
 #pragma unroll
-    for (int d = 1; d < kLanes; d <<= 1) {
-        const int t0 = __shfl_up(in0, d), t1 = __shfl_up(in1, d);
-        if (lane >= d) {
-            in0 += t0;
-            in1 += t1;
+        for (int u = 0; u < 2; ++u) {
+            const int r = pre[u] - seg;
+            if (len[u] > 0 && r >= 0 && r < kStreamSeg)
+                atomicOr(reinterpret_cast<unsigned *>(s_bits) + (r >> 5), 1u << (r & 31));
         }
-    }
-    const int tot0 = __shfl(in0, kLanes - 1);
-    const int pre_lo = in0 - l0, pre_hi = tot0 + in1 - l1;
-    const int total = tot0 + __shfl(in1, kLanes - 1);
-    if (lane < kStencil) s_pre[lane] = pre_lo;
-    if (lane + kLanes < kStencil) s_pre[lane + kLanes] = pre_hi;
-    __syncthreads();
-    // One stream of candidates: the neighbour ranges in offset order, 64 at a
-    // time.  Lane l takes candidate P0 + l, in the last offset whose prefix is
-    // <= P0 + l; the offsets that start inside the chunk are walked once per
-    // chunk (wave-uniform), starting from the offset that held the previous
-    // chunk's last candidate.
-    int cur = 0;
-    for (int P0 = 0; P0 < total; P0 += kLanes) {
-        const int p = P0 + lane;
-        const bool valid = p < total;
-        int o = cur;
-        for (int k = cur + 1; k < kStencil; ++k) {
-            const int pk = k < kLanes ? __builtin_amdgcn_readlane(pre_lo, k) : __builtin_amdgcn_readlane(pre_hi, k - kLanes);
-            if (pk >= P0 + kLanes) break;
-            o += p >= pk ? 1 : 0;
-        }
-        cur = __builtin_amdgcn_readlane(o, kLanes - 1);
-        const int j = valid ? s_start[o] + (p - s_pre[o]) : 0;
-        const d4 q = pq[j];
-        const double px = q.a + s_sx[o], py = q.b + s_sy[o], pz = q.c + s_sz[o];
-        const uint32_t entry = (uint32_t)j | ((uint32_t)s_code[o] << kPairIndexBits);
-        const int self = (valid && o == kCenter) ? j : -1;  // the home cell without shift
+        __syncthreads();
+        const int seg_end = total - seg < kStreamSeg ? total : seg + kStreamSeg;
+        for (int P0 = seg; P0 < seg_end; P0 += kLanes) {
+            const uint64_t mv = s_bits[(P0 - seg) >> 6];
+            // readfirstlane works on 32-bit ints: zero-extend each half
+            const uint32_t m_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)mv);
+            const uint32_t m_hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(mv >> 32));
+            const uint64_t m = ((uint64_t)m_hi << 32) | (uint64_t)m_lo;
+            const int below = (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            const int k = base + below + (int)((m >> lane) & 1u) - 1;
+            base += __popcll(m);
+            const int p = P0 + lane;
+            const bool valid = p < total;
+            const int j = valid ? s_start[k] + (p - s_pre[k]) : 0;
+            const d4 q = pq[j];
+            // lanes past the stream's end sit at an infinite distance (r2
+            // overflows to +inf), so the cutoff test alone rejects them
+            const double far = valid ? 0.0 : 1e300;
+            const double px = q.a + s_sx[k] + far, py = q.b + s_sy[k], pz = q.c + s_sz[k];
+            const uint32_t entry = (uint32_t)j | ((uint32_t)s_code[k] << kPairIndexBits);
+            const int self = k == self_ord ? j : -1;  // the home cell without shift
 #pragma unroll
-        for (int h = 0; h < kPairHome; ++h) {
-            if (h < nh) {
-                const double dx = hx[h] - px, dy = hy[h] - py, dz = hz[h] - pz;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                const bool in = valid && r2 < rc2 && self != i0 + h;
-                const uint64_t m = __ballot(in);
-                int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                                  __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-                pos = pos < cap ? pos : cap - 1;  // an overflowing list is not used
-                if (in) list[(size_t)(i0 + h) * cap + pos] = entry;
-                cnt[h] += __popcll(m);
+            for (int h = 0; h < kPairHome; ++h) {
+                if (h < nh) {
+                    const double dx = hx[h] - px, dy = hy[h] - py, dz = hz[h] - pz;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const bool in = (r2 < rc2) & (self != i0 + h);
+                    const uint64_t mk = __builtin_amdgcn_ballot_w64(in);
+                    if (mk != 0) {  // wave-uniform: most chunks hold no pair of most homes
+                        int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi(
+                                               (unsigned)(mk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
+                        pos = pos < cap ? pos : cap - 1;  // an overflowing list is not used
+                        if (in) list[(size_t)(i0 + h) * cap + pos] = entry;
+                        cnt[h] += __popcll(mk);
+                    }
+                }
             }
         }
     }

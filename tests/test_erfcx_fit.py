@@ -1,0 +1,68 @@
+"""The FP32 polynomial behind the mixed-precision real-space kernel:
+erfc(x) exp(x^2) ~= t P(t), t = 1 / (1 + x / 2), with the coefficients the
+kernel compiles in (read from its header).  Checked against SciPy's erfcx, in
+exact arithmetic and with the kernel's FP32 Horner evaluation emulated."""
+import pathlib
+import re
+
+import numpy as np
+import pytest
+from scipy.special import erfc, erfcx
+
+HDR = pathlib.Path(__file__).resolve().parents[1] / "paper_1708_01135_amd" / "csrc" / "erfcx_fit.h"
+
+
+def _coeffs():
+    txt = HDR.read_text()
+    t_scale = float(re.search(r"kErfcxT\s*=\s*([0-9.eE+-]+)f", txt).group(1))
+    deg = int(re.search(r"kErfcxDegree\s*=\s*(\d+)", txt).group(1))
+    body = txt[txt.index("kErfcxP[kErfcxDegree + 1] = {"):]
+    body = body[body.index("{") + 1:body.index("};")]
+    vals = [float.fromhex(m) for m in re.findall(r"(-?0x[0-9a-fA-Fp.+-]+)f", body)]
+    assert len(vals) == deg + 1
+    return t_scale, np.array(vals, dtype=np.float32)
+
+
+def _fma32(a, b, c):
+    # a*b of two FP32 values is exact in FP64; one rounding to FP32 after the add
+    return np.float32(np.float64(a) * np.float64(b) + np.float64(c))
+
+
+def _eval_fp32(x):
+    p, c = _coeffs()
+    x = np.asarray(x, dtype=np.float32)
+    t = np.float32(1.0) / (np.float32(1.0) + np.float32(p) * x)
+    acc = np.full_like(x, c[-1])
+    for ci in c[-2::-1]:
+        acc = _fma32(acc, t, ci)
+    return (acc * t).astype(np.float32)
+
+
+def test_coefficients_are_fp32_and_lead_term_matches_asymptote():
+    p, c = _coeffs()
+    assert c.dtype == np.float32
+    # x -> infinity: erfcx(x) ~ 1 / (sqrt(pi) x) and t ~ 1 / (p x), so P(0) -> p / sqrt(pi)
+    assert abs(float(c[0]) - p / np.sqrt(np.pi)) < 2e-6
+
+
+def test_fit_relative_error_exact_arithmetic():
+    p, c = _coeffs()
+    x = np.concatenate([np.linspace(0.0, 12.0, 240001), np.geomspace(12.0, 1e7, 20001)])
+    t = 1.0 / (1.0 + p * x)
+    approx = np.polyval(np.float64(c)[::-1], t) * t
+    assert np.max(np.abs(approx / erfcx(x) - 1.0)) < 1e-7
+
+
+@pytest.mark.parametrize("lo,hi", [(0.0, 1.0), (1.0, 4.0), (4.0, 8.0)])
+def test_fp32_evaluation_error(lo, hi):
+    x = np.linspace(lo, hi, 100001)
+    rel = np.abs(_eval_fp32(x).astype(np.float64) / erfcx(x) - 1.0)
+    assert np.max(rel) < 5e-7
+
+
+def test_erfc_reconstruction_over_ewald_range():
+    # erfc(x) = exp(-x^2) erfcx(x): the product the kernel forms, for the
+    # real-space arguments sqrt(alpha) r of typical plans (x up to ~4.5)
+    x = np.linspace(0.05, 4.5, 20001)
+    rec = np.exp(-x * x) * _eval_fp32(x).astype(np.float64)
+    assert np.max(np.abs(rec / erfc(x) - 1.0)) < 5e-7
