@@ -74,7 +74,8 @@ def parse():
 # Kernel-source files whose hash is stored with the counter-based traffic figures;
 # a changed source invalidates them.
 KERNEL_SOURCES = {"gather": "paper_1708_01135_amd/csrc/k_gather_mfma.hip",
-                  "sk": "paper_1708_01135_amd/csrc/k_sk_mfma.hip", "pair": "paper_1708_01135_amd/csrc/k_pair.hip"}
+                  "sk": "paper_1708_01135_amd/csrc/k_sk_mfma.hip", "pair": "paper_1708_01135_amd/csrc/k_pair.hip",
+                  "pair_list": "paper_1708_01135_amd/csrc/k_pair.hip"}
 
 
 def source_hash(kernel):
