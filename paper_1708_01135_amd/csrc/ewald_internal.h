@@ -144,9 +144,11 @@ constexpr int kSmNatWide = 3;  // the 16-row variant, k_max <= 8 kSmNatWide - 1
 constexpr int kSmStage = 5;  // staged table entries per thread: 3 P KP <= kSmStage * kSmWaves * kLanes
 int sk_mfma_particles(int KP);
 size_t sk_mfma_smem_bytes(int KP);
+// tile_of[block * kSmWaves + w]: the tile (of 8 rows, or 16 in the wide variant)
+// of wave w in row block `block`, or -1.
 hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_groups, int n_chunks, int chunk_len,
                           const c64 *tx, const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny,
-                          const int *row_m, const int *unit_base, d4 *part);
+                          const int *row_m, const int *unit_base, const int *tile_of, d4 *part);
 // particles per block of the matrix-core gather (16 per sub-tile)
 template <typename R>
 constexpr int mfma_block_particles()

@@ -12,8 +12,12 @@
 //
 // Rows are taken in the structure-factor order (sorted by m, 64 to a group);
 // a wave owns a tile of 8 consecutive rows and accumulates every block of 8
-// a values the tile needs; a block of kSmWaves waves covers one group of 64
-// rows and one particle chunk.  The block stages the q x^n, y^n and z^n tables
+// a values the tile needs; a block of kSmWaves waves covers kSmWaves tiles and
+// one particle chunk.  The plan deals the tiles to (block, wave) so that the
+// two waves sharing a SIMD (w and w + 4) pair a heavy tile with a light one
+// and every block gets a similar mix: the waves of a block meet at a barrier
+// after every staged sub-chunk, so a block runs at the pace of its busiest
+// SIMD.  The block stages the q x^n, y^n and z^n tables
 // of P particles at a time in LDS (32, or 16 for k_max >= 24).  The partial sums of the chunk are
 // written in the slot layout of the vector kernel (unit = (row group, a
 // segment), a mod 8, row mod 64), so the same fixed-order reduction follows.
@@ -65,7 +69,8 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma(int64_t n, int 
                                                               const int *__restrict__ row_nx,
                                                               const int *__restrict__ row_ny,
                                                               const int *__restrict__ row_m,
-                                                              const int *__restrict__ unit_base, int n_slots,
+                                                              const int *__restrict__ unit_base,
+                                                              const int *__restrict__ tile_of, int n_slots,
                                                               d4 *__restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -81,7 +86,10 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma(int64_t n, int 
 
     const int lane = (int)threadIdx.x & (kLanes - 1);
     const int w = (int)threadIdx.x / kLanes;
-    const int tile_row0 = grp * kLanes + w * kSmRows;  // first row of the wave's tile
+    // first row of the wave's tile (tiles are dealt to waves by the plan so that
+    // the block's SIMD pairs carry similar work; -1: no tile)
+    const int tt = tile_of[grp * kSmWaves + w];
+    const int tile_row0 = tt < 0 ? n_rows : tt * kSmRows;
     // A operand: row tile_row0 + (lane % 8), component lane / 8 % 2 of U
     const int ra = tile_row0 + (lane & 7);
     const bool ra_ok = ra < n_rows;
@@ -175,7 +183,7 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma(int64_t n, int 
             const double v1 = bim ? ur + ui : ur - ui;
             const double v2 = bim ? ui - ur : ur + ui;
             if (r < n_rows) {
-                const int unit = unit_base[grp] + b;
+                const int unit = unit_base[r / kLanes] + b;
                 const int slot = (unit * kQ + bofs) * kLanes + (r & (kLanes - 1));
                 double *o = reinterpret_cast<double *>(part + (size_t)chunk * n_slots + slot);
                 o[bim] = v1;
@@ -225,7 +233,8 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n,
                                                                      const int *__restrict__ row_nx,
                                                                      const int *__restrict__ row_ny,
                                                                      const int *__restrict__ row_m,
-                                                                     const int *__restrict__ unit_base, int n_slots,
+                                                                     const int *__restrict__ unit_base,
+                                                                     const int *__restrict__ tile_of, int n_slots,
                                                                      d4 *__restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -239,7 +248,8 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n,
 
     const int lane = (int)threadIdx.x & (kLanes - 1);
     const int w = (int)threadIdx.x / kLanes;
-    const int tile_row0 = rblk * (2 * kLanes) + w * 16;  // first of the wave's 16 rows
+    const int tt = tile_of[rblk * kSmWaves + w];  // the wave's 16-row tile (-1: none)
+    const int tile_row0 = tt < 0 ? n_rows : tt * 16;
     // A operand: row tile_row0 + lane % 16 (both parts of its U)
     const int ra = tile_row0 + (lane & 15);
     const bool ra_ok = ra < n_rows;
@@ -341,19 +351,19 @@ size_t sk_mfma_smem_bytes(int KP) { return (size_t)3 * sk_mfma_particles(KP) * K
 
 hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_groups, int n_chunks, int chunk_len,
                           const c64 *tx, const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny,
-                          const int *row_m, const int *unit_base, d4 *part)
+                          const int *row_m, const int *unit_base, const int *tile_of, d4 *part)
 {
     const int P = sk_mfma_particles(a.KP);
     if (a.KP <= kSmRows * kSmNatWide) {
         const int n_rblocks = (a.n_rows + 2 * kLanes - 1) / (2 * kLanes);
         hipLaunchKernelGGL(k_sk_mfma_wide, dim3(xcd_grid(n_rblocks * n_chunks)), dim3(kSmWaves * kLanes),
                            sk_mfma_smem_bytes(a.KP), s, a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty,
-                           tz, row_nx, row_ny, row_m, unit_base, a.n_slots, part);
+                           tz, row_nx, row_ny, row_m, unit_base, tile_of, a.n_slots, part);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_sk_mfma, dim3(xcd_grid(n_groups * n_chunks)), dim3(kSmWaves * kLanes), sk_mfma_smem_bytes(a.KP),
                        s, a.n, a.KP, P, a.n_rows, n_groups, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m,
-                       unit_base, a.n_slots, part);
+                       unit_base, tile_of, a.n_slots, part);
     return hipGetLastError();
 }
 

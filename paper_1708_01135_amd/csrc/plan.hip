@@ -43,6 +43,7 @@ struct KLayout {
     std::vector<int64_t> nap_prefix; // prefix sums of the tiles' a pairs
     int m_blocks = 0, nap_max = 0;
     std::vector<int> unit_base;      // first structure-factor unit of each 64-row group
+    std::vector<int> sk_tile_of;     // matrix-core structure factor: tile of (row block, wave), or -1
 };
 
 int isqrt_floor(int v)
@@ -57,6 +58,29 @@ int isqrt_floor(int v)
 // group g, register r (the FP32 one returns row 4 g + r); the tile rows of a
 // quad's n_y offsets follow the instruction the plan will use, so that lane
 // group g always holds quad g.
+// Tiles of the matrix-core structure factor dealt to (row block, wave).  Tiles
+// (8 rows, or 16 for the wide variant, in the structure-factor order) are
+// sorted by their blocks of a, heaviest first.  Waves w and w + 4 of a block
+// share a SIMD: the i-th heaviest tile is paired with the i-th lightest (slots
+// past the last tile are empty), and the pairs are dealt round-robin over the
+// row blocks, so every block's busiest SIMD carries about the average load.
+void build_sk_tiles(KLayout &kl)
+{
+    const bool wide = kl.KP <= kSmRows * kSmNatWide;
+    const int rows_per_tile = wide ? 16 : kSmRows;
+    const int n_tiles = (kl.n_rows + rows_per_tile - 1) / rows_per_tile;
+    const int n_rb = (n_tiles + kSmWaves - 1) / kSmWaves;
+    const int slots = n_rb * kSmWaves;
+    const int half = kSmWaves / 2;
+    kl.sk_tile_of.assign(slots, -1);
+    for (int pr = 0; pr < slots / 2; ++pr) {
+        const int heavy = pr, light = slots - 1 - pr;
+        const int blk = pr % n_rb, k = pr / n_rb;  // k-th pair of block blk: waves k and k + half
+        kl.sk_tile_of[blk * kSmWaves + k] = heavy < n_tiles ? heavy : -1;
+        kl.sk_tile_of[blk * kSmWaves + k + half] = light < n_tiles ? light : -1;
+    }
+}
+
 void build_klayout(int K, KLayout &kl, bool fp64_rows = false)
 {
     kl.K = K;
@@ -163,6 +187,7 @@ void build_klayout(int K, KLayout &kl, bool fp64_rows = false)
         kl.nap_prefix.push_back(kl.nap_prefix.back() + tl.nap);
         kl.mtiles.push_back(tl);
     }
+    build_sk_tiles(kl);
 }
 
 // Cells per axis for the pair loop: side h = L / nc >= r_c / kPairReach.
@@ -246,7 +271,7 @@ struct Sizes {
     size_t tx, part, sk, rec, gpart;
     size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
     size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
-    size_t mcoef, mtiles, row_mbase, unit_base, pr;
+    size_t mcoef, mtiles, row_mbase, unit_base, sk_tile_of, pr;
     size_t total;
     int max_chunks;
     int max_pitems;  // pair work items: cells + n/kPairHome bounds sum_c ceil(count_c / kPairHome)
@@ -308,8 +333,9 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.mtiles = align_up(sizeof(MTile) * kl.mtiles.size());
     z.row_mbase = align_up(sizeof(int) * (size_t)kl.n_rows);
     z.unit_base = align_up(sizeof(int) * kl.unit_base.size());
+    z.sk_tile_of = align_up(sizeof(int) * kl.sk_tile_of.size());
     z.pr = align_up(sizeof(d4) * N);
-    z.total = z.pr + z.mcoef + z.mtiles + z.row_mbase + z.unit_base + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
+    z.total = z.pr + z.mcoef + z.mtiles + z.row_mbase + z.unit_base + z.sk_tile_of + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
               z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
               3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx;
 }
@@ -349,6 +375,7 @@ struct ewald_plan_s {
     MTile *mtiles = nullptr;
     int *row_mbase = nullptr;
     int *unit_base = nullptr;
+    int *sk_tile_of = nullptr;
     d4 *pr = nullptr;  // caller-order particle records of the reciprocal kernels
     bool mfma_gather = false, mfma_sk = false;
     // profiling
@@ -573,6 +600,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->mtiles = carve<MTile>(cur, z.mtiles);
     p->row_mbase = carve<int>(cur, z.row_mbase);
     p->unit_base = carve<int>(cur, z.unit_base);
+    p->sk_tile_of = carve<int>(cur, z.sk_tile_of);
     p->pr = carve<d4>(cur, z.pr);
     p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmRows * kSmNat &&
                  sk_mfma_particles(p->kl.KP) >= 8;
@@ -604,6 +632,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (e == hipSuccess) e = upload(p->mtiles, kl.mtiles, s);
     if (e == hipSuccess) e = upload(p->row_mbase, kl.row_mbase, s);
     if (e == hipSuccess) e = upload(p->unit_base, kl.unit_base, s);
+    if (e == hipSuccess) e = upload(p->sk_tile_of, kl.sk_tile_of, s);
     // padding entries of the tile coefficients are never written and stay zero
     if (e == hipSuccess) e = hipMemsetAsync(p->mcoef, 0, z.mcoef, s);
     // counters start at zero; afterwards every evaluation leaves them cleared
@@ -692,7 +721,7 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
         run(ax, KC_SK, [&] {
             if (p->mfma_sk)
                 return launch_sk_mfma(ax, ra, n_groups, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
-                                      p->row_m, p->unit_base, p->part);
+                                      p->row_m, p->unit_base, p->sk_tile_of, p->part);
             return launch_sk(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
                              p->part);
         });
