@@ -2,7 +2,9 @@
 
 All HIP sources are compiled with packed-FP32 instruction selection disabled
 (``-target-feature -packed-fp32-ops``); the kernels are written for plain
-64-wide wavefront VALU/scalar execution on CDNA4.
+64-wide wavefront VALU/scalar execution on CDNA4.  MFMA results are kept in
+VGPRs (``-amdgpu-mfma-vgpr-form``): the gather's epilogue reads every
+accumulator, and the AGPR form cost a copy per value and two waves per SIMD.
 """
 import glob
 import os
@@ -26,6 +28,7 @@ def build(verbose: bool = False, extra=None) -> str:
     srcs = sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           "-mllvm", "-amdgpu-mfma-vgpr-form=1",
            "-Wall", "-Wno-unused-function",
            "-I", os.path.join(ROOT, "include"), "-o", LIB + ".tmp"] + srcs + list(extra or [])
     if verbose:

@@ -153,7 +153,7 @@ hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_groups, int n
 template <typename R>
 constexpr int mfma_block_particles()
 {
-    return sizeof(R) == 4 ? 64 : 32;
+    return sizeof(R) == 4 ? 32 : 32;
 }
 size_t gather_mfma_smem_bytes(int nap_max, bool fp64);
 template <typename R>
