@@ -158,10 +158,6 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     for (int t = lo + w; t < hi; t += kGmWaves) {
         const MTile tl = tiles[t];
         V acc[4][NSUB];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int s = 0; s < NSUB; ++s) acc[q][s] = V{0, 0, 0, 0};
         const R *cb = coef + (size_t)tl.base * kMBlock + lane;
         // operands two a pairs ahead, in three named register sets (the loop is
         // unrolled by three, so no set is copied and each load has a whole pair
@@ -182,11 +178,31 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
                 acc[3][s] = Mfma<R>::mma(c[3], z[s], acc[3][s]);
             }
         };
-        const int nap = tl.nap, last = nap - 1;
+        // the first a pair starts the accumulators (zero C operand)
+        auto mfma_first = [&](const R (&c)[4], const R (&z)[NSUB]) {
+#pragma unroll
+            for (int s = 0; s < NSUB; ++s) {
+                acc[0][s] = Mfma<R>::mma(c[0], z[s], V{0, 0, 0, 0});
+                acc[1][s] = Mfma<R>::mma(c[1], z[s], V{0, 0, 0, 0});
+                acc[2][s] = Mfma<R>::mma(c[2], z[s], V{0, 0, 0, 0});
+                acc[3][s] = Mfma<R>::mma(c[3], z[s], V{0, 0, 0, 0});
+            }
+        };
+        const int nap = tl.nap, last = nap - 1;  // nap >= 1
         R c0[4], z0[NSUB], c1[4], z1[NSUB], c2[4], z2[NSUB];
         load_pair(0, c0, z0);
         load_pair(last < 1 ? last : 1, c1, z1);
-        for (int p = 0; p < nap; p += 3) {
+        load_pair(last < 2 ? last : 2, c2, z2);
+        mfma_first(c0, z0);
+        if (1 < nap) {
+            load_pair(last < 3 ? last : 3, c0, z0);
+            mfma_pair(c1, z1);
+        }
+        if (2 < nap) {
+            load_pair(last < 4 ? last : 4, c1, z1);
+            mfma_pair(c2, z2);
+        }
+        for (int p = 3; p < nap; p += 3) {
             load_pair(p + 2 < last ? p + 2 : last, c2, z2);
             mfma_pair(c0, z0);
             if (p + 1 < nap) {
