@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server measurement")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="plans launch kernel by kernel (no graph replay of repeated evaluations)")
     ap.add_argument("--serving-systems", type=int, default=256)
     ap.add_argument("--serving-passes", type=int, default=3)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -257,7 +259,8 @@ def main():
     results = {}
     precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     for prec in precisions:
-        plan = ewald.Plan(n, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, prec)
+        plan = ewald.Plan(n, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, prec,
+                          flags=ewald.FLAG_NO_GRAPH if args.no_graph else 0)
         out = (torch.empty(5, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
                torch.empty(n, dtype=torch.float64, device=dev))
         ms = time_steps(plan, pos, q, out, args.steps, args.warmup)

@@ -35,6 +35,19 @@
  *     work enqueued on the plan's stream after a call still sees all of that
  *     call's results and may overwrite its inputs.  Host-detectable errors
  *     return before anything is enqueued.  No call aborts the process.
+ *   - Graph replay: the key of an evaluation is its n, buffers (pos, q and
+ *     every output pointer) and kind (energy and forces, energy only, or
+ *     backward with its grad_energy pointer).  The plan remembers the last 4
+ *     distinct keys; the second evaluation with a remembered key captures the
+ *     launch sequence into a HIP graph (on a plan-owned capture stream, so the
+ *     plan's stream may be the null stream) and later ones launch that graph
+ *     onto the plan's stream when that stream is idle (hipStreamQuery): the
+ *     graph saves host launch time, which only a call on an idle stream waits
+ *     for; behind queued work the kernels are launched one by one.  The graph
+ *     runs the same kernels with the same arguments, so results are bitwise
+ *     those of the kernel-by-kernel launch.  Any other call launches kernel by
+ *     kernel; so do profiled calls and plans made with EWALD_FLAG_NO_GRAPH, and
+ *     a plan whose capture failed once (it then never tries again).
  *   - A plan is not re-entrant: calls on one plan must not overlap.  Distinct
  *     plans may be used concurrently on distinct streams.
  *   - Results are bitwise reproducible for identical inputs, plan and device
@@ -90,7 +103,10 @@ enum {
  *                EWALD_FLAG_VALU_GATHER  reciprocal force gather on the vector ALUs,
  *                EWALD_FLAG_VALU_SK      structure factor on the vector ALUs,
  *              instead of the matrix cores (same results to rounding; used to
- *              compare the two).  Other bits are invalid.  The vector kernels are
+ *              compare the two), and
+ *                EWALD_FLAG_NO_GRAPH     always launch kernel by kernel (see
+ *                                        "Graph replay" below).
+ *              Other bits are invalid.  The vector kernels are
  *              also used where the matrix-core ones do not fit: the gather when a
  *              block's staged z powers would exceed 64 KB of LDS (FP64 with
  *              k_max > 83), the structure factor for k_max > 47. */
@@ -109,6 +125,7 @@ typedef struct {
 #define EWALD_K_MAX_LIMIT 100
 #define EWALD_FLAG_VALU_GATHER 1
 #define EWALD_FLAG_VALU_SK 2
+#define EWALD_FLAG_NO_GRAPH 4
 
 /* Static description of a status code (never NULL). */
 const char *ewald_status_string(ewald_status status);

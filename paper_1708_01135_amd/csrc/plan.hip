@@ -354,6 +354,7 @@ struct ewald_plan_s {
     // joined back to the caller's stream, concurrently with the real-space ones
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_done = nullptr;  // after the last graph-mode evaluation on the plan's stream
     int device = 0;
     bool mixed = false;
     int nc = 1, ncell = 1;
@@ -378,6 +379,28 @@ struct ewald_plan_s {
     int *sk_tile_of = nullptr;
     d4 *pr = nullptr;  // caller-order particle records of the reciprocal kernels
     bool mfma_gather = false, mfma_sk = false;
+    // graph replay of repeated evaluations (same n, buffers and kind)
+    struct GraphKey {
+        int64_t n = -1;
+        const void *pos = nullptr, *q = nullptr, *energy = nullptr, *forces = nullptr, *dEdq = nullptr,
+                   *gscale = nullptr;
+        bool energy_only = false;
+        bool operator==(const GraphKey &o) const
+        {
+            return n == o.n && pos == o.pos && q == o.q && energy == o.energy && forces == o.forces &&
+                   dEdq == o.dEdq && gscale == o.gscale && energy_only == o.energy_only;
+        }
+    };
+    struct GraphSlot {
+        GraphKey key;
+        hipGraphExec_t exec = nullptr;  // null until the key is seen a second time
+        uint64_t used = 0;
+    };
+    static constexpr size_t kGraphSlots = 4;  // distinct keys kept (least recently used goes)
+    bool graphs = true;          // false: plan flag, or a capture failed
+    hipStream_t cap = nullptr;   // capture stream (the caller's may be the null stream)
+    std::vector<GraphSlot> gslots;
+    uint64_t gclock = 0;
     // profiling
     bool prof = false;
     std::vector<ProfRec> pending;
@@ -488,7 +511,8 @@ ewald_status ewald_params_validate(const ewald_params *p)
     if (!(std::isfinite(p->r_c) && p->r_c > 0.0 && p->r_c <= p->box_L)) return EWALD_ERR_INVALID_ARG;
     if (p->k_max < 1 || p->k_max > EWALD_K_MAX_LIMIT) return EWALD_ERR_INVALID_ARG;
     if (p->precision != EWALD_PRECISION_FP64 && p->precision != EWALD_PRECISION_MIXED) return EWALD_ERR_INVALID_ARG;
-    if (p->device < 0 || (p->flags & ~(EWALD_FLAG_VALU_GATHER | EWALD_FLAG_VALU_SK)) != 0) return EWALD_ERR_INVALID_ARG;
+    if (p->device < 0 || (p->flags & ~(EWALD_FLAG_VALU_GATHER | EWALD_FLAG_VALU_SK | EWALD_FLAG_NO_GRAPH)) != 0)
+        return EWALD_ERR_INVALID_ARG;
     return EWALD_OK;
 }
 
@@ -550,10 +574,14 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
         return EWALD_ERR_OUT_OF_MEMORY;
     }
     if (hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
+        if (p->ev_join) (void)hipEventDestroy(p->ev_join);
         if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+        if (p->cap) (void)hipStreamDestroy(p->cap);
         if (p->aux) (void)hipStreamDestroy(p->aux);
         (void)hipFree(p->base);
         delete p;
@@ -602,6 +630,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->unit_base = carve<int>(cur, z.unit_base);
     p->sk_tile_of = carve<int>(cur, z.sk_tile_of);
     p->pr = carve<d4>(cur, z.pr);
+    p->graphs = !(params->flags & EWALD_FLAG_NO_GRAPH);
     p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmRows * kSmNat &&
                  sk_mfma_particles(p->kl.KP) >= 8;
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
@@ -645,6 +674,8 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
         (void)hipGetLastError();
         (void)hipEventDestroy(p->ev_fork);
         (void)hipEventDestroy(p->ev_join);
+        (void)hipEventDestroy(p->ev_done);
+        (void)hipStreamDestroy(p->cap);
         (void)hipStreamDestroy(p->aux);
         (void)hipFree(p->base);
         delete p;
@@ -665,16 +696,13 @@ ewald_status ewald_plan_set_stream(ewald_plan_t plan, void *stream)
 
 namespace {
 
-// The whole evaluation on the plan's stream.  energy_only skips the force
-// gather (the reciprocal energy comes from the structure factor alone);
-// gscale, when given, turns the force / dE/dq outputs into the adjoint.
-ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy, double *forces,
-                      double *dEdq, const double *gscale, bool energy_only)
+// The whole evaluation enqueued on stream s (the plan's stream, or its capture
+// stream while a graph is recorded).  energy_only skips the force gather (the
+// reciprocal energy comes from the structure factor alone); gscale, when
+// given, turns the force / dE/dq outputs into the adjoint.
+ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double *pos, const double *q,
+                         double *energy, double *forces, double *dEdq, const double *gscale, bool energy_only)
 {
-    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
-    DeviceGuard dg(p->device);
-    if (!dg.ok()) return EWALD_ERR_DEVICE;
-    hipStream_t s = p->stream;
     const KLayout &kl = p->kl;
     const double L = p->prm.box_L;
 
@@ -790,6 +818,92 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     return EWALD_OK;
 }
 
+// Kernel-by-kernel launch, or graph replay when the evaluation repeats an
+// earlier one's key (one of the last kGraphSlots distinct keys): the second
+// evaluation with a key records the launch sequence on the capture stream (the
+// reciprocal stream joins the capture through the fork event) and every later
+// one on an idle stream launches that graph.
+ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy, double *forces,
+                      double *dEdq, const double *gscale, bool energy_only)
+{
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    if (p->prof || !p->graphs) return launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+    ewald_plan_s::GraphKey key;
+    key.n = n;
+    key.pos = pos;
+    key.q = q;
+    key.energy = energy;
+    key.forces = forces;
+    key.dEdq = dEdq;
+    key.gscale = gscale;
+    key.energy_only = energy_only;
+    // every graph-mode evaluation ends with the completion event
+    auto finish = [&](ewald_status st) {
+        if (st == EWALD_OK && hipEventRecord(p->ev_done, p->stream) != hipSuccess) st = EWALD_ERR_DEVICE;
+        return st;
+    };
+    ewald_plan_s::GraphSlot *slot = nullptr;
+    for (auto &sl : p->gslots)
+        if (sl.key == key) slot = &sl;
+    if (!slot) {
+        // first sight of this key: remember it (evicting the least recently used)
+        if (p->gslots.size() < ewald_plan_s::kGraphSlots) {
+            p->gslots.emplace_back();
+            slot = &p->gslots.back();
+        } else {
+            slot = &p->gslots[0];
+            for (auto &sl : p->gslots)
+                if (sl.used < slot->used) slot = &sl;
+            if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+            slot->exec = nullptr;
+        }
+        slot->key = key;
+        slot->used = ++p->gclock;
+        return finish(launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only));
+    }
+    slot->used = ++p->gclock;
+    if (slot->exec) {
+        // A graph launch saves host launch time, which is what a call on an idle
+        // stream waits for; with work already queued the kernels run faster
+        // launched one by one (measured at 32^3: 0.235 against 0.242 ms back to
+        // back, 0.28 against 0.26 ms per synchronised call), so the graph is
+        // used only on an idle stream.
+        // Idle: the previous evaluation's completion event (recorded after it on
+        // the plan's stream) has fired.
+        const hipError_t busy = hipEventQuery(p->ev_done);
+        if (busy == hipErrorNotReady) {
+            (void)hipGetLastError();
+            return finish(launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only));
+        }
+        return finish(hipGraphLaunch(slot->exec, p->stream) == hipSuccess ? EWALD_OK : EWALD_ERR_DEVICE);
+    }
+    // second evaluation with this key: record it
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ewald_status st = EWALD_ERR_DEVICE;
+    if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+        st = launch_path(p, p->cap, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+        const hipError_t ec = hipStreamEndCapture(p->cap, &g);
+        if (ec != hipSuccess || !g) st = EWALD_ERR_DEVICE;
+        if (st == EWALD_OK && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+            x = nullptr;
+            st = EWALD_ERR_DEVICE;
+        }
+        if (g) (void)hipGraphDestroy(g);
+    }
+    if (st != EWALD_OK || !x) {
+        // no graphs for this plan: launch kernel by kernel from now on
+        (void)hipGetLastError();
+        if (x) (void)hipGraphExecDestroy(x);
+        p->graphs = false;
+        return launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+    }
+    slot->exec = x;
+    return finish(hipGraphLaunch(x, p->stream) == hipSuccess ? EWALD_OK : EWALD_ERR_DEVICE);
+}
+
 }  // namespace
 
 extern "C" {
@@ -840,8 +954,12 @@ void ewald_release(ewald_plan_t p)
         DeviceGuard dg(p->device);
         (void)hipStreamSynchronize(p->stream);
         (void)hipStreamSynchronize(p->aux);
+        for (const auto &slot : p->gslots)
+            if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
         (void)hipEventDestroy(p->ev_fork);
         (void)hipEventDestroy(p->ev_join);
+        (void)hipEventDestroy(p->ev_done);
+        (void)hipStreamDestroy(p->cap);
         (void)hipStreamDestroy(p->aux);
         for (const ProfRec &r : p->pending) {
             (void)hipEventDestroy(r.a);

@@ -27,6 +27,7 @@ MIXED = 1
 K_MAX_LIMIT = 100
 FLAG_VALU_GATHER = 1
 FLAG_VALU_SK = 2
+FLAG_NO_GRAPH = 4
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
 

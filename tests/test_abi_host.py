@@ -39,7 +39,7 @@ def test_status_strings():
 BAD = [
     dict(n_max=0), dict(n_max=(1 << 25) + 1), dict(box_L=0.0), dict(box_L=-1.0), dict(box_L=float("nan")), dict(alpha=0.0),
     dict(alpha=float("inf")), dict(r_c=0.0), dict(r_c=8.5), dict(k_max=0), dict(k_max=ew.K_MAX_LIMIT + 1),
-    dict(precision=2), dict(device=-1), dict(flags=4), dict(flags=-1),
+    dict(precision=2), dict(device=-1), dict(flags=8), dict(flags=-1),
 ]
 
 
@@ -55,8 +55,9 @@ def test_invalid_parameters_rejected_without_gpu(bad):
     assert h.value is None  # *out cleared on failure
 
 
-def test_vector_alu_flags_are_valid():
-    for f in (ew.FLAG_VALU_GATHER, ew.FLAG_VALU_SK, ew.FLAG_VALU_GATHER | ew.FLAG_VALU_SK):
+def test_vector_alu_and_graph_flags_are_valid():
+    for f in (ew.FLAG_VALU_GATHER, ew.FLAG_VALU_SK, ew.FLAG_VALU_GATHER | ew.FLAG_VALU_SK, ew.FLAG_NO_GRAPH,
+              ew.FLAG_VALU_GATHER | ew.FLAG_VALU_SK | ew.FLAG_NO_GRAPH):
         assert ew.validate(ew.make_params(512, 8.0, 0.9, 4.0, 8, flags=f)) == ew.OK
     p = ew.make_params(512, 8.0, 0.9, 4.0, 8, flags=ew.FLAG_VALU_GATHER)
     assert ew.workspace_bytes(p) == ew.workspace_bytes(ew.make_params(512, 8.0, 0.9, 4.0, 8))
