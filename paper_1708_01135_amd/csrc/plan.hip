@@ -354,7 +354,8 @@ struct ewald_plan_s {
     // joined back to the caller's stream, concurrently with the real-space ones
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    hipEvent_t ev_done = nullptr;  // after the last graph-mode evaluation on the plan's stream
+    hipEvent_t ev_done = nullptr;  // recorded after each graph launch on the plan's stream
+    bool last_graph = false;       // the previous evaluation was a graph launch
     int device = 0;
     bool mixed = false;
     int nc = 1, ncell = 1;
@@ -839,10 +840,18 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     key.dEdq = dEdq;
     key.gscale = gscale;
     key.energy_only = energy_only;
-    // every graph-mode evaluation ends with the completion event
-    auto finish = [&](ewald_status st) {
-        if (st == EWALD_OK && hipEventRecord(p->ev_done, p->stream) != hipSuccess) st = EWALD_ERR_DEVICE;
-        return st;
+    // A graph launch is followed by the completion event; a kernel-by-kernel
+    // evaluation already records the join event at the end of its reciprocal
+    // chain, which serves as its (nearly complete) marker.  No marker is added
+    // to the eager path, so back-to-back evaluations keep their packet stream.
+    auto eager = [&]() {
+        p->last_graph = false;
+        return launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+    };
+    auto graph = [&](hipGraphExec_t x) {
+        p->last_graph = true;
+        if (hipGraphLaunch(x, p->stream) != hipSuccess) return EWALD_ERR_DEVICE;
+        return hipEventRecord(p->ev_done, p->stream) == hipSuccess ? EWALD_OK : EWALD_ERR_DEVICE;
     };
     ewald_plan_s::GraphSlot *slot = nullptr;
     for (auto &sl : p->gslots)
@@ -861,7 +870,7 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
         }
         slot->key = key;
         slot->used = ++p->gclock;
-        return finish(launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only));
+        return eager();
     }
     slot->used = ++p->gclock;
     if (slot->exec) {
@@ -870,14 +879,13 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
         // launched one by one (measured at 32^3: 0.235 against 0.242 ms back to
         // back, 0.28 against 0.26 ms per synchronised call), so the graph is
         // used only on an idle stream.
-        // Idle: the previous evaluation's completion event (recorded after it on
-        // the plan's stream) has fired.
-        const hipError_t busy = hipEventQuery(p->ev_done);
+        // Idle: the previous evaluation's marker has fired.
+        const hipError_t busy = hipEventQuery(p->last_graph ? p->ev_done : p->ev_join);
         if (busy == hipErrorNotReady) {
             (void)hipGetLastError();
-            return finish(launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only));
+            return eager();
         }
-        return finish(hipGraphLaunch(slot->exec, p->stream) == hipSuccess ? EWALD_OK : EWALD_ERR_DEVICE);
+        return graph(slot->exec);
     }
     // second evaluation with this key: record it
     hipGraph_t g = nullptr;
@@ -898,10 +906,10 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
         (void)hipGetLastError();
         if (x) (void)hipGraphExecDestroy(x);
         p->graphs = false;
-        return launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+        return eager();
     }
     slot->exec = x;
-    return finish(hipGraphLaunch(x, p->stream) == hipSuccess ? EWALD_OK : EWALD_ERR_DEVICE);
+    return graph(x);
 }
 
 }  // namespace
