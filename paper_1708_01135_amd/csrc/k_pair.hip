@@ -23,7 +23,9 @@
 // particle whose list would overflow is evaluated by the exact direct loop
 // instead.
 //
-// Precision: FP64 computes everything in double.  MIXED forms d and |d|^2 in
+// Precision: FP64 computes everything in double (erfc as exp(-x^2) times an FP64
+// polynomial fit of erfc(x) exp(x^2) when sqrt(alpha) r_c <= 8, the library erfc
+// otherwise).  MIXED forms d and |d|^2 in
 // FP64 (exact cutoff test, no cancellation), evaluates the pair terms in FP32
 // (erfc as exp(-x^2) times a polynomial fit of erfc(x) exp(x^2), the Gaussian
 // from the FP64 exponent), and accumulates phi and F in FP64.
@@ -75,11 +77,28 @@ __device__ inline float erfcx_f32(float x)
     return acc * t;
 }
 
+// erfc(x) exp(x^2) for 0 <= x <= kErfcx64XMax in FP64 (polynomial in the centred
+// u of t = 1 / (1 + x / 2), coefficients in erfcx_fit.h); 1/d by the hardware
+// reciprocal and two Newton steps.
+__device__ inline double erfcx_f64(double x)
+{
+    const double d = fma(0.5, x, 1.0);
+    double t = __builtin_amdgcn_rcp(d);
+    t = fma(t, fma(-d, t, 1.0), t);
+    t = fma(t, fma(-d, t, 1.0), t);
+    const double u = (t - kErfcx64C) * kErfcx64InvH;
+    double acc = kErfcx64Q[kErfcx64Degree];
+#pragma unroll
+    for (int i = kErfcx64Degree - 1; i >= 0; --i) acc = fma(acc, u, kErfcx64Q[i]);
+    return acc * t;
+}
+
 // One pair inside the cutoff: accumulate phi += q_j erfc(sa r)/r and
 // F += q_j [erfc(sa r)/r + 2 sqrt(a/pi) exp(-a r^2)] / r^2 * d (q_i applied later).
 // MIXED writes erfc(sa r) = exp(-a r^2) erfcx(sa r), so the one Gaussian serves
-// both terms.
-template <bool MIXED>
+// both terms; so does FP64 when FIT64 (sqrt(a) r_c within the FP64 fit's range),
+// with 1/r from the hardware reciprocal square root and two Newton steps.
+template <bool MIXED, bool FIT64>
 __device__ inline void pair_term(double dx, double dy, double dz, double r2, double qj, const PairConsts &k,
                                  double &ph, double &fx, double &fy, double &fz)
 {
@@ -92,6 +111,17 @@ __device__ inline void pair_term(double dx, double dy, double dz, double r2, dou
         const float qf = (float)qj;
         const double f = (double)(qf * (ec + gg) * (ri * ri));
         ph += (double)(qf * ec);
+        fx += f * dx;
+        fy += f * dy;
+        fz += f * dz;
+    } else if constexpr (FIT64) {
+        double ri = __builtin_amdgcn_rsq(r2);
+        ri = fma(0.5 * ri, fma(-r2 * ri, ri, 1.0), ri);
+        ri = fma(0.5 * ri, fma(-r2 * ri, ri, 1.0), ri);
+        const double e = exp(-k.alpha * r2);
+        const double ec = e * erfcx_f64(k.sa * (r2 * ri)) * ri;
+        const double f = qj * (ec + k.tsap * e) * (ri * ri);
+        ph += qj * ec;
         fx += f * dx;
         fy += f * dy;
         fz += f * dz;
@@ -295,7 +325,7 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
 
 // Evaluation pass: a work item is any kPairHome consecutive particles (lists
 // carry global indices and image-shift codes, so no per-cell table is needed).
-template <bool MIXED>
+template <bool MIXED, bool FIT64>
 __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double rc2, double alpha,
                                              const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                              const uint32_t *__restrict__ list, const int *__restrict__ list_cnt,
@@ -344,7 +374,7 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
                 const double dx = (me.a - s_sh[code][0]) - p[u].a;
                 const double dy = (me.b - s_sh[code][1]) - p[u].b;
                 const double dz = (me.c - s_sh[code][2]) - p[u].c;
-                pair_term<MIXED>(dx, dy, dz, dx * dx + dy * dy + dz * dz, p[u].d, k, ph, fx, fy, fz);
+                pair_term<MIXED, FIT64>(dx, dy, dz, dx * dx + dy * dy + dz * dz, p[u].d, k, ph, fx, fy, fz);
             }
         }
     }
@@ -363,7 +393,7 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
                 const d4 p = pq[j];
                 const double dx = xi - p.a, dy = yi - p.b, dz = zi - p.c;
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2 && !(o == kCenter && j == i)) pair_term<MIXED>(dx, dy, dz, r2, p.d, k, ph, fx, fy, fz);
+                if (r2 < rc2 && !(o == kCenter && j == i)) pair_term<MIXED, FIT64>(dx, dy, dz, r2, p.d, k, ph, fx, fy, fz);
             }
         }
     }
@@ -400,12 +430,17 @@ hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *
                        const uint32_t *list, const int *list_cnt, int cap, d4 *freal)
 {
     const int blocks = xcd_grid(ceil_div(a.n, kPairHome));
+    // the FP64 erfcx polynomial covers sqrt(alpha) r <= kErfcx64XMax
+    const bool fit64 = sqrt(a.alpha * a.rc2) <= kErfcx64XMax;
     if (mixed)
-        hipLaunchKernelGGL(k_pair<true>, dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq,
-                           list, list_cnt, cap, freal);
+        hipLaunchKernelGGL((k_pair<true, false>), dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha,
+                           cell_start, pq, list, list_cnt, cap, freal);
+    else if (fit64)
+        hipLaunchKernelGGL((k_pair<false, true>), dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha,
+                           cell_start, pq, list, list_cnt, cap, freal);
     else
-        hipLaunchKernelGGL(k_pair<false>, dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq,
-                           list, list_cnt, cap, freal);
+        hipLaunchKernelGGL((k_pair<false, false>), dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha,
+                           cell_start, pq, list, list_cnt, cap, freal);
     return hipGetLastError();
 }
 

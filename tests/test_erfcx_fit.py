@@ -66,3 +66,41 @@ def test_erfc_reconstruction_over_ewald_range():
     x = np.linspace(0.05, 4.5, 20001)
     rec = np.exp(-x * x) * _eval_fp32(x).astype(np.float64)
     assert np.max(np.abs(rec / erfc(x) - 1.0)) < 5e-7
+
+
+def _coeffs64():
+    txt = HDR.read_text()
+    def const(name):
+        return float.fromhex(re.search(name + r"\s*=\s*(-?0x[0-9a-fA-Fp.+-]+);", txt).group(1))
+    xmax = float(re.search(r"kErfcx64XMax\s*=\s*([0-9.eE+-]+);", txt).group(1))
+    deg = int(re.search(r"kErfcx64Degree\s*=\s*(\d+)", txt).group(1))
+    body = txt[txt.index("kErfcx64Q[kErfcx64Degree + 1] = {"):]
+    body = body[body.index("{") + 1:body.index("};")]
+    vals = [float.fromhex(m) for m in re.findall(r"(-?0x[0-9a-fA-Fp.+-]+),", body)]
+    assert len(vals) == deg + 1
+    return xmax, const("kErfcx64C"), const("kErfcx64InvH"), np.array(vals)
+
+
+def _eval_fp64(x):
+    _, c, inv_h, q = _coeffs64()
+    t = 1.0 / (1.0 + 0.5 * x)
+    u = (t - c) * inv_h
+    acc = np.full_like(x, q[-1])
+    for v in q[-2::-1]:
+        acc = acc * u + v
+    return acc * t
+
+
+def test_fp64_fit_covers_its_range_to_near_double_precision():
+    xmax, c, inv_h, q = _coeffs64()
+    # the centred variable spans [-1, 1] over x in [0, xmax]
+    assert abs((1.0 - c) * inv_h - 1.0) < 1e-12
+    assert abs((1.0 / (1.0 + 0.5 * xmax) - c) * inv_h + 1.0) < 1e-12
+    x = np.linspace(0.0, xmax, 400001)
+    assert np.max(np.abs(_eval_fp64(x) / erfcx(x) - 1.0)) < 2e-14
+
+
+def test_fp64_erfc_reconstruction():
+    x = np.linspace(0.05, 6.0, 100001)
+    rec = np.exp(-x * x) * _eval_fp64(x)
+    assert np.max(np.abs(rec / erfc(x) - 1.0)) < 1e-13
