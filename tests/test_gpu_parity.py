@@ -29,6 +29,8 @@ SMALL_CASES = [
     ("odd_ragged", 1001, 10.0, 0.9, 3.2, 9),               # nc = 3, ragged tail
     ("k_row_boundaries", 777, 9.0, 1.0, 3.0, 16),          # K a multiple of the segment width
     ("k_17", 513, 8.0, 0.8, 2.6, 17),
+    ("steep_gaussian_fit_edge", 400, 9.5, 3.0, 4.6, 12),   # sqrt(alpha) r_c = 7.97: FP64 fit near its end
+    ("steep_gaussian_library", 400, 9.5, 4.0, 4.2, 12),    # sqrt(alpha) r_c = 8.4: FP64 library erfc
 ]
 
 
