@@ -14,7 +14,7 @@
 //  * k_phase   builds per-particle tables of exp(i n theta_a), n = 0..KP-1, for the
 //              three axes (x table pre-multiplied by q), in the caller's particle
 //              order.  Powers come from FP64 recurrences: exp(i theta) inside blocks
-//              of kQ, exp(i kQ theta) from block to block, both from FP64 sincos.
+//              of kQ, exp(i 2 kQ theta) from block to block, from FP64 sincos.
 //  * k_sk      one block = one "unit" (64 rows x one segment of kQ values a = |n_z|)
 //              times one particle chunk.  Lanes own rows; the particle loop is
 //              wave-uniform, so exp(i a theta_z) for the segment is read through the
@@ -46,31 +46,34 @@ __device__ inline typename Cplx<R>::type make_c(double re, double im)
 }
 
 // ------------------------------------------------------------------ k_phase
-// One thread per table row (particle j, axis): two FP64 sincos (theta and
-// kQ theta); the powers inside each block of kQ follow the FP64 recurrence from
-// the block's anchor, and the anchors advance by exp(i kQ theta) (at most
-// kQ + KP / kQ rounding steps from an exact value).  The block's rows are
-// staged in LDS and stored with consecutive threads on consecutive entries.
+// Two threads per table row (particle j, axis), each with two FP64 sincos
+// (theta and kQ theta): thread h fills the blocks of kQ powers b = h, h + 2, ...
+// The powers inside a block follow the FP64 recurrence from the block's anchor
+// q exp(i kQ b theta); the anchors start at exp(i kQ h theta) and advance by
+// exp(i 2 kQ theta) (at most kQ + KP / (2 kQ) + 1 rounding steps from an exact
+// value).  The block's rows are staged in LDS and stored with consecutive
+// threads on consecutive entries.
 template <typename R>
-__global__ __launch_bounds__(kPhaseRows) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
-                                                      const double *__restrict__ qv, d4 *__restrict__ pr,
-                                                      typename Cplx<R>::type *__restrict__ tx,
-                                                      typename Cplx<R>::type *__restrict__ ty,
-                                                      typename Cplx<R>::type *__restrict__ tz)
+__global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
+                                                          const double *__restrict__ qv, d4 *__restrict__ pr,
+                                                          typename Cplx<R>::type *__restrict__ tx,
+                                                          typename Cplx<R>::type *__restrict__ ty,
+                                                          typename Cplx<R>::type *__restrict__ tz)
 {
     using C = typename Cplx<R>::type;
     extern __shared__ __align__(16) unsigned char smem[];
     C *buf = reinterpret_cast<C *>(smem);  // [rows of the block][KP]
-    const int rows = (int)blockDim.x;
+    const int rows = (int)blockDim.x / 2;
+    const int lr = (int)threadIdx.x >> 1, h = (int)threadIdx.x & 1;
     const int64_t total = n * 3;
     const int64_t r0 = (int64_t)blockIdx.x * rows;
-    const int64_t row = r0 + threadIdx.x;
+    const int64_t row = r0 + lr;
     if (row < total) {
         const int ax = (int)(row % 3);
         const int64_t j = row / 3;
         const double qj = qv[j];
         const double x = wrap_coord(pos[3 * j + ax], L);
-        if (ax == 0) {
+        if (ax == 0 && h == 0) {
             d4 r;
             r.a = x;
             r.b = wrap_coord(pos[3 * j + 1], L);
@@ -83,9 +86,11 @@ __global__ __launch_bounds__(kPhaseRows) void k_phase(int64_t n, double L, int K
         sincos(th, &s1, &c1);
         sincos((double)kQ * th, &s8, &c8);
         const double scale = ax == 0 ? qj : 1.0;
-        double ar = scale, ai = 0.0;  // anchor q exp(i kQ b theta)
-        C *dst = buf + (size_t)threadIdx.x * KP;
-        for (int b = 0; b < KP; b += kQ) {
+        // anchor q exp(i kQ b theta) of block b = h; step exp(i 2 kQ theta)
+        double ar = h ? scale * c8 : scale, ai = h ? scale * s8 : 0.0;
+        const double c16 = c8 * c8 - s8 * s8, s16 = 2.0 * s8 * c8;
+        C *dst = buf + (size_t)lr * KP;
+        for (int b = kQ * h; b < KP; b += 2 * kQ) {
             double pr_ = ar, pi_ = ai;
 #pragma unroll
             for (int k = 0; k < kQ; ++k) {
@@ -94,17 +99,17 @@ __global__ __launch_bounds__(kPhaseRows) void k_phase(int64_t n, double L, int K
                 pi_ = pr_ * s1 + pi_ * c1;
                 pr_ = nr;
             }
-            const double na = ar * c8 - ai * s8;
-            ai = ar * s8 + ai * c8;
+            const double na = ar * c16 - ai * s16;
+            ai = ar * s16 + ai * c16;
             ar = na;
         }
     }
     __syncthreads();
     const int64_t nrows = total - r0 < rows ? total - r0 : rows;
     const int count = (int)nrows * KP;
-    for (int e = (int)threadIdx.x; e < count; e += rows) {
-        const int lr = e / KP, k = e - lr * KP;
-        const int64_t rg = r0 + lr;
+    for (int e = (int)threadIdx.x; e < count; e += (int)blockDim.x) {
+        const int er = e / KP, k = e - er * KP;
+        const int64_t rg = r0 + er;
         const int ax = (int)(rg % 3);
         const int64_t j = rg / 3;
         C *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + j * KP + k;
@@ -545,7 +550,7 @@ hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, co
     int rows = kPhaseRows;
     while (rows > 1 && (size_t)rows * a.KP * sizeof(typename Cplx<R>::type) > 64 * 1024) rows /= 2;
     const int64_t total = a.n * 3;
-    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, rows)), dim3(rows),
+    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, rows)), dim3(2 * rows),
                        (size_t)rows * a.KP * sizeof(typename Cplx<R>::type), s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
                        tz);
     return hipGetLastError();
