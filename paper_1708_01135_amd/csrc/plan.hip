@@ -222,9 +222,19 @@ int gather_split(int64_t n)
 // chip, at least two tiles per wave on average; split boundaries balance the
 // tiles' a pairs.
 constexpr int kMfmaTargetBlocks = 1024;
-// blocks of kSmWaves waves: two resident per CU (the kernel is built for four
-// waves per SIMD), one round over the 256 CUs
-constexpr int kSkMfmaTargetBlocks = 512;
+// Blocks of kSmWaves waves in one round over the 256 CUs: one per CU for the
+// 16-row variant, two per CU (four waves per SIMD) for the 8-row one.  The
+// 16-row kernel runs beside the real-space kernels, and one block per CU left
+// them more of each SIMD: rock salt 32^3 (k_max 20) took 0.231 instead of
+// 0.236 ms per evaluation, although the structure factor alone took 87.5
+// instead of 82 us.  The 8-row kernel (k_max >= 24) needs the second block:
+// 3.4 instead of 2.5 ms alone at 64^3 (k_max 32).  A count between the two
+// leaves some CUs with one block and others with two (98 us at 32^3).
+constexpr int kSkMfmaBlocksPerCu[2] = {2, 1};  // [8-row kernel, 16-row kernel]
+int sk_mfma_target_blocks(const KLayout &kl)
+{
+    return 256 * kSkMfmaBlocksPerCu[kl.KP <= kSmRows * kSmNatWide ? 1 : 0];
+}
 
 // Row blocks of the matrix-core structure factor: 128-row blocks for the wide
 // variant (k_max <= 8 kSmNatWide - 1), 64-row groups otherwise.
@@ -237,7 +247,7 @@ int sk_mfma_row_blocks(const KLayout &kl)
 // Particle chunks the matrix-core structure factor may use (partial-sum capacity).
 int sk_mfma_chunk_cap(const KLayout &kl)
 {
-    return std::max(1, std::min(kMaxChunks, kSkMfmaTargetBlocks / sk_mfma_row_blocks(kl)));
+    return std::max(1, std::min(kMaxChunks, sk_mfma_target_blocks(kl) / sk_mfma_row_blocks(kl)));
 }
 
 int gather_mfma_split(int64_t n, const KLayout &kl, bool fp64)
@@ -715,7 +725,7 @@ ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double 
     if (p->mfma_sk) {
         // particle chunks of the matrix-core structure factor: fill the chip, at
         // most the partial-sum capacity, at least one staged tile per chunk
-        int64_t c = kSkMfmaTargetBlocks / sk_mfma_row_blocks(kl);
+        int64_t c = sk_mfma_target_blocks(kl) / sk_mfma_row_blocks(kl);
         c = std::min<int64_t>(c, p->sz.max_chunks);
         c = std::min<int64_t>(c, (n + sk_mfma_particles(kl.KP) - 1) / sk_mfma_particles(kl.KP));
         n_chunks = (int)std::max<int64_t>(c, 1);
