@@ -92,3 +92,43 @@ def test_energy_only_and_backward_replays():
         assert torch.equal(gp, gpr) and torch.equal(gq, gqr) and torch.equal(e, er), it
         gs.mul_(1.5)  # the upstream gradient changes in place
     assert g.status() == ew.OK
+
+
+def test_two_plans_on_side_streams_replay():
+    """Two plans on two non-default streams, evaluated alternately many times
+    (graph replay on both), each equal to its kernel-by-kernel reference."""
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    dev = torch.device("cuda:0")
+    systems = [_system(1500, 21), _system(2200, 22)]
+    streams = [torch.cuda.Stream(device=dev), torch.cuda.Stream(device=dev)]  # default priority
+    plans, refs, bufs, outs = [], [], [], []
+    for (pos_h, q_h, L, alpha, rc, K), st in zip(systems, streams):
+        n = q_h.shape[0]
+        pos = torch.tensor(pos_h, device=dev)
+        q = torch.tensor(q_h, device=dev)
+        r = ew.Plan(n, L, alpha, rc, K, "mixed", flags=ew.FLAG_NO_GRAPH)
+        e, f, d = r.energy_forces(pos, q, True, True)
+        torch.cuda.synchronize()
+        refs.append((e.clone(), f.clone(), d.clone()))
+        with torch.cuda.stream(st):
+            plans.append(ew.Plan(n, L, alpha, rc, K, "mixed"))
+        bufs.append((pos, q))
+        outs.append((torch.empty(5, dtype=torch.float64, device=dev),
+                     torch.empty((n, 3), dtype=torch.float64, device=dev),
+                     torch.empty(n, dtype=torch.float64, device=dev)))
+    torch.cuda.synchronize()
+    for it in range(6):
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                plans[k].energy_forces(bufs[k][0], bufs[k][1], True, True, out=outs[k])
+        if it % 2:
+            torch.cuda.synchronize()
+            for k in range(2):
+                for a, b in zip(outs[k], refs[k]):
+                    assert torch.equal(a, b), (it, k)
+    torch.cuda.synchronize()
+    for k in range(2):
+        for a, b in zip(outs[k], refs[k]):
+            assert torch.equal(a, b), k
+        assert plans[k].status() == ew.OK
