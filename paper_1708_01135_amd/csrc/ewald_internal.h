@@ -141,7 +141,9 @@ constexpr int kSmWaves = kLanes / 8;
 constexpr int kSmRows = 8;
 constexpr int kSmNat = 6;
 constexpr int kSmNatWide = 3;  // the 16-row variant, k_max <= 8 kSmNatWide - 1
+constexpr int kSmNapWide = kSmRows * kSmNatWide / 2;  // its pairs of a values per row
 constexpr int kSmStage = 5;  // staged table entries per thread: 3 P KP <= kSmStage * kSmWaves * kLanes
+constexpr int kSmStageWide = 7;  // the same for the 16-row variant
 int sk_mfma_particles(int KP);
 size_t sk_mfma_smem_bytes(int KP);
 // tile_of[block * kSmWaves + w]: the tile (of 8 rows, or 16 in the wide variant)

@@ -7,8 +7,9 @@
 // P3 = sum Re U Im z, P4 = sum Im U Re z:
 //   S(+a) = (P1 - P2, P3 + P4),  S(-a) = (P1 + P2, P4 - P3).
 // Over particles that is a real matrix product [rows x (Re U, Im U)] .
-// [(Re z^a, Im z^a) x a], evaluated with 16x16x4 FP64 MFMAs: M = 8 rows x
-// (Re U, Im U), N = 8 values of a x (Re z, Im z), K = 4 particles.
+// [(Re z^a, Im z^a) x a].  For k_max >= 24 it is evaluated with 16x16x4 FP64
+// MFMAs: M = 8 rows x (Re U, Im U), N = 8 values of a x (Re z, Im z), K = 4
+// particles; for k_max <= 23 with 4x4x4 FP64 MFMAs (the wide variant below).
 //
 // Rows are taken in the structure-factor order (sorted by m, 64 to a group);
 // a wave owns a tile of 8 consecutive rows and accumulates every block of 8
@@ -18,7 +19,7 @@
 // and every block gets a similar mix: the waves of a block meet at a barrier
 // after every staged sub-chunk, so a block runs at the pace of its busiest
 // SIMD.  The block stages the q x^n, y^n and z^n tables
-// of P particles at a time in LDS (32, or 16 for k_max >= 24).  The partial sums of the chunk are
+// of P particles at a time in LDS (sk_mfma_particles).  The partial sums of the chunk are
 // written in the slot layout of the vector kernel (unit = (row group, a
 // segment), a mod 8, row mod 64), so the same fixed-order reduction follows.
 #include "ewald_internal.h"
@@ -193,18 +194,21 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma(int64_t n, int 
     }
 }
 
-// Wide-tile variant for k_max <= 23 (at most three blocks of 8 values of a per
-// row): a wave owns 16 rows and issues two MFMAs per quad and block of a, one
-// with Re U and one with Im U as the A operand, so every lane forms the U of a
-// distinct (row, particle) and every z read feeds two MFMAs -- half the LDS
-// traffic per MFMA of the 8-row tiles.  A block of kSmWaves waves covers two
-// row groups (128 rows).  Output register r of lane l holds row (l / 16) + 4 r
-// of the tile against column ((l % 16) / 2, l % 2): Re U z (re part) and Im U z
-// (im part); with the partner lane l ^ 1 they give S(+a) and S(-a).
-template <int NAT>
+// Wide-tile variant for k_max <= 23, on the FP64 4x4x4 instruction (four
+// independent 4x4x4 products per instruction, block g = (l / 4) % 4): a wave owns
+// 16 rows and takes the values of a two at a time.  Lane l supplies A = U of row
+// l % 16 (block (l / 4) % 4, A row l % 4) for particle l / 16 of the quad (the
+// K index), and B = component l % 2 of z^(2b + (l % 4) / 2) of the same particle
+// (every block gets the same B); two instructions per quad and pair b, one with
+// Re U and one with Im U.  The output of lane l is row 4 ((l / 4) % 4) + l / 16
+// of the tile against column l % 4.  Pairs of a waste at most one column of a
+// row (the 8-wide blocks of the 16x16x4 form wasted 22 % of the (row, a) pairs
+// at k_max = 20), and on this part the 4x4x4 instruction sustains about 1.45x
+// the FP64 rate of the 16x16x4 one.
+template <int NAP>
 __device__ __forceinline__ void sk_wide_pass(const c64 *__restrict__ st, int per, int KP, int P, int nx, int ay,
-                                             double ysg, int kq, int bofs, int bim, dv4 (&are)[kSmNatWide],
-                                             dv4 (&aim)[kSmNatWide])
+                                             double ysg, int kq, int zc, double (&are)[kSmNapWide],
+                                             double (&aim)[kSmNapWide])
 {
     for (int pq = 0; pq < P; pq += 4) {
         const int p = pq + kq;
@@ -213,19 +217,19 @@ __device__ __forceinline__ void sk_wide_pass(const c64 *__restrict__ st, int per
         const double yi = ysg * yv.im;
         const double ur = xv.re * yv.re - xv.im * yi;
         const double ui = xv.re * yi + xv.im * yv.re;
-        const double *zrow = reinterpret_cast<const double *>(st + 2 * per + p * KP + bofs) + bim;
-        double z[NAT];
+        const double *zrow = reinterpret_cast<const double *>(st + 2 * per + p * KP) + zc;
+        double z[NAP];
 #pragma unroll
-        for (int b = 0; b < NAT; ++b) z[b] = zrow[2 * kSmRows * b];
+        for (int b = 0; b < NAP; ++b) z[b] = zrow[4 * b];
 #pragma unroll
-        for (int b = 0; b < NAT; ++b) {
-            are[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ur, z[b], are[b], 0, 0, 0);
-            aim[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(ui, z[b], aim[b], 0, 0, 0);
+        for (int b = 0; b < NAP; ++b) {
+            are[b] = __builtin_amdgcn_mfma_f64_4x4x4f64(ur, z[b], are[b], 0, 0, 0);
+            aim[b] = __builtin_amdgcn_mfma_f64_4x4x4f64(ui, z[b], aim[b], 0, 0, 0);
         }
     }
 }
 
-__global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n, int KP, int P, int n_rows,
+__global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma_wide(int64_t n, int KP, int P, int n_rows,
                                                                      int n_rblocks, int n_chunks, int chunk_len,
                                                                      const c64 *__restrict__ tx,
                                                                      const c64 *__restrict__ ty,
@@ -257,33 +261,34 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n,
     const int nyv = ra_ok ? row_ny[ra] : 0;
     const int ay = nyv < 0 ? -nyv : nyv;
     const double ysg = nyv < 0 ? -1.0 : 1.0;
-    const int bofs = (lane & 15) >> 1, bim = lane & 1;
+    const int zc = lane & 3;  // B column: z^(2b + zc / 2), component zc % 2
     const int kq = lane >> 4;
-    const int nat = tile_row0 < n_rows ? (row_m[tile_row0] + kSmRows) / kSmRows : 0;
+    const int nap = tile_row0 < n_rows ? (row_m[tile_row0] + 2) / 2 : 0;  // pairs of a values
 
-    dv4 are[kSmNatWide], aim[kSmNatWide];
+    double are[kSmNapWide], aim[kSmNapWide];
 #pragma unroll
-    for (int b = 0; b < kSmNatWide; ++b) are[b] = aim[b] = dv4{0, 0, 0, 0};
+    for (int b = 0; b < kSmNapWide; ++b) are[b] = aim[b] = 0.0;
 
+    // Staging as in the 8-row kernel, kSmStageWide entries per thread.
     const int per = P * KP;
     constexpr int kStride = kSmWaves * kLanes;
-    const c64 *sbase[kSmStage];
-    int soff[kSmStage];
-    bool suse[kSmStage];
+    const c64 *sbase[kSmStageWide];
+    int soff[kSmStageWide];
+    bool suse[kSmStageWide];
 #pragma unroll
-    for (int u = 0; u < kSmStage; ++u) {
+    for (int u = 0; u < kSmStageWide; ++u) {
         const int e = (int)threadIdx.x + u * kStride;
         const int tab = e < per ? 0 : (e < 2 * per ? 1 : 2);
         suse[u] = e < 3 * per;
         soff[u] = e - tab * per;
         sbase[u] = tab == 0 ? tx : (tab == 1 ? ty : tz);
     }
-    c64 v[kSmStage];
+    c64 v[kSmStageWide];
     auto valid_of = [&](int64_t j0) { return (int)((j_hi - j0 < P ? j_hi - j0 : P) * KP); };
     auto load_stage = [&](int64_t j0) {
         const int valid = valid_of(j0);
 #pragma unroll
-        for (int u = 0; u < kSmStage; ++u) {
+        for (int u = 0; u < kSmStageWide; ++u) {
             const bool ok = suse[u] && soff[u] < valid;
             v[u] = sbase[u][j0 * KP + (ok ? soff[u] : 0)];
         }
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n,
         __syncthreads();
         const int valid = valid_of(j0);
 #pragma unroll
-        for (int u = 0; u < kSmStage; ++u) {
+        for (int u = 0; u < kSmStageWide; ++u) {
             if (suse[u]) {
                 const bool ok = soff[u] < valid;
                 c64 t;
@@ -304,46 +309,57 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 4) void k_sk_mfma_wide(int64_t n,
         }
         __syncthreads();
         if (j0 + P < j_hi) load_stage(j0 + P);
-        switch (nat) {  // wave-uniform
-        case 1: sk_wide_pass<1>(st, per, KP, P, nx, ay, ysg, kq, bofs, bim, are, aim); break;
-        case 2: sk_wide_pass<2>(st, per, KP, P, nx, ay, ysg, kq, bofs, bim, are, aim); break;
-        case 3: sk_wide_pass<3>(st, per, KP, P, nx, ay, ysg, kq, bofs, bim, are, aim); break;
+        switch (nap) {  // wave-uniform
+        case 1: sk_wide_pass<1>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 2: sk_wide_pass<2>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 3: sk_wide_pass<3>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 4: sk_wide_pass<4>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 5: sk_wide_pass<5>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 6: sk_wide_pass<6>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 7: sk_wide_pass<7>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 8: sk_wide_pass<8>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 9: sk_wide_pass<9>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 10: sk_wide_pass<10>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 11: sk_wide_pass<11>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
+        case 12: sk_wide_pass<12>(st, per, KP, P, nx, ay, ysg, kq, zc, are, aim); break;
         default: break;
         }
     }
 
-    const int g = lane >> 4;
+    // lane l: row 4 ((l / 4) % 4) + l / 16 of the tile, a = 2b + (l % 4) / 2,
+    // component l % 2; the partner lane l ^ 1 holds the other z component
+    const int r = tile_row0 + 4 * ((lane >> 2) & 3) + (lane >> 4);
+    const int aoff = (lane >> 1) & 1, bim = lane & 1;
 #pragma unroll
-    for (int b = 0; b < kSmNatWide; ++b) {
-        if (b >= nat) break;
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-            const int r = tile_row0 + g + 4 * h;
-            const double ur = are[b][h];
-            const double ui = __shfl_xor(aim[b][h], 1);  // partner's Im U with the other z part
-            // Re z column: S+re = P1 - P2, S-re = P1 + P2;  Im z column: S+im = P3 + P4, S-im = P4 - P3
-            const double v1 = bim ? ur + ui : ur - ui;
-            const double v2 = bim ? ui - ur : ur + ui;
-            if (r < n_rows) {
-                const int unit = unit_base[r / kLanes] + b;
-                const int slot = (unit * kQ + bofs) * kLanes + (r & (kLanes - 1));
-                double *o = reinterpret_cast<double *>(part + (size_t)chunk * n_slots + slot);
-                o[bim] = v1;
-                o[2 + bim] = v2;
-            }
+    for (int b = 0; b < kSmNapWide; ++b) {
+        const double ur = are[b];
+        const double ui = __shfl_xor(aim[b], 1);  // partner's Im U with the other z part
+        // Re z column: S+re = P1 - P2, S-re = P1 + P2;  Im z column: S+im = P3 + P4, S-im = P4 - P3
+        const double v1 = bim ? ur + ui : ur - ui;
+        const double v2 = bim ? ui - ur : ur + ui;
+        const int a = 2 * b + aoff;
+        if (b < nap && r < n_rows) {
+            const int unit = unit_base[r / kLanes] + (a >> 3);
+            const int slot = (unit * kQ + (a & 7)) * kLanes + (r & (kLanes - 1));
+            double *o = reinterpret_cast<double *>(part + (size_t)chunk * n_slots + slot);
+            o[bim] = v1;
+            o[2 + bim] = v2;
         }
     }
 }
 
 }  // namespace
 
-// Particles per staged sub-chunk: the largest of 32, 16, 8 whose three tables
-// (3 P KP entries) fit kSmStage entries per thread; a multiple of 8 (two quads
-// per step).  0 if even 8 do not fit.
+// Particles per staged sub-chunk: the largest of 64, 48 (16-row kernel only),
+// 32, 16, 8 whose three tables (3 P KP entries) fit the kernel's staged entries
+// per thread; a multiple of 8 (two quads per step).  0 if even 8 do not fit.
 int sk_mfma_particles(int KP)
 {
-    for (int P = 32; P >= 8; P /= 2)
-        if (3 * P * KP <= kSmStage * kSmWaves * kLanes) return P;
+    const bool wide = KP <= kSmRows * kSmNatWide;
+    const int cap = (wide ? kSmStageWide : kSmStage) * kSmWaves * kLanes;
+    static const int kCand[5] = {64, 48, 32, 16, 8};
+    for (int c = wide ? 0 : 2; c < 5; ++c)
+        if (3 * kCand[c] * KP <= cap) return kCand[c];
     return 0;
 }
 

@@ -225,9 +225,8 @@ constexpr int kMfmaTargetBlocks = 1024;
 // Blocks of kSmWaves waves in one round over the 256 CUs: one per CU for the
 // 16-row variant, two per CU (four waves per SIMD) for the 8-row one.  The
 // 16-row kernel runs beside the real-space kernels, and one block per CU left
-// them more of each SIMD: rock salt 32^3 (k_max 20) took 0.231 instead of
-// 0.236 ms per evaluation, although the structure factor alone took 87.5
-// instead of 82 us.  The 8-row kernel (k_max >= 24) needs the second block:
+// them more of each SIMD: rock salt 32^3 (k_max 20) took 0.218 instead of
+// 0.223 ms per evaluation.  The 8-row kernel (k_max >= 24) needs the second block:
 // 3.4 instead of 2.5 ms alone at 64^3 (k_max 32).  A count between the two
 // leaves some CUs with one block and others with two (98 us at 32^3).
 constexpr int kSkMfmaBlocksPerCu[2] = {2, 1};  // [8-row kernel, 16-row kernel]
