@@ -134,23 +134,22 @@ hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, con
                             const int *unit_group, const int *unit_seg, const int *row_nx,
                             const int *row_ny, const int *row_m, const int *row_item, const double *ck,
                             d4 *sk, R *rec, R *mcoef, const int *row_mbase, double *erec_part);
-// Matrix-core structure factor (k_sk_mfma.hip): one block per (64-row group,
-// particle chunk), one wave per 8-row tile holding up to kSmNat blocks of 8
-// values of a in FP64 MFMA accumulators (k_max <= 8 kSmNat - 1).
+// Matrix-core structure factor (k_sk_mfma.hip): one block per (128 rows,
+// particle chunk), one wave per 16-row tile holding up to kSmNap pairs of a
+// values in FP64 MFMA accumulators (k_max <= 2 kSmNap - 1).
 constexpr int kSmWaves = kLanes / 8;
-constexpr int kSmRows = 8;
-constexpr int kSmNat = 6;
-constexpr int kSmNatWide = 3;  // the 16-row variant, k_max <= 8 kSmNatWide - 1
-constexpr int kSmNapWide = kSmRows * kSmNatWide / 2;  // its pairs of a values per row
-constexpr int kSmStage = 5;  // staged table entries per thread: 3 P KP <= kSmStage * kSmWaves * kLanes
-constexpr int kSmStageWide = 7;  // the same for the 16-row variant
+constexpr int kSmTileRows = 16;
+constexpr int kSmNap = 24;
+constexpr int kSmNapSmall = 12;  // the instance for KP <= 2 kSmNapSmall
+constexpr int kSmMaxKP = 2 * kSmNap;  // k_max + 1 <= KP <= kSmMaxKP
+constexpr int kSmStage = 9;  // staged entries per thread, a multiple of 3: 3 P KP <= kSmStage * kSmWaves * kLanes
 int sk_mfma_particles(int KP);
 size_t sk_mfma_smem_bytes(int KP);
-// tile_of[block * kSmWaves + w]: the tile (of 8 rows, or 16 in the wide variant)
-// of wave w in row block `block`, or -1.
-hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_groups, int n_chunks, int chunk_len,
-                          const c64 *tx, const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny,
-                          const int *row_m, const int *unit_base, const int *tile_of, d4 *part);
+inline int sk_mfma_row_blocks(int n_rows) { return (n_rows + kSmWaves * kSmTileRows - 1) / (kSmWaves * kSmTileRows); }
+// tile_of[block * kSmWaves + w]: the 16-row tile of wave w in row block `block`, or -1.
+hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx,
+                          const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny, const int *row_m,
+                          const int *unit_base, const int *tile_of, d4 *part);
 // particles per block of the matrix-core gather (16 per sub-tile)
 template <typename R>
 constexpr int mfma_block_particles()

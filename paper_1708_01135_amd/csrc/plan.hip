@@ -59,15 +59,14 @@ int isqrt_floor(int v)
 // quad's n_y offsets follow the instruction the plan will use, so that lane
 // group g always holds quad g.
 // Tiles of the matrix-core structure factor dealt to (row block, wave).  Tiles
-// (8 rows, or 16 for the wide variant, in the structure-factor order) are
+// (16 rows in the structure-factor order) are
 // sorted by their blocks of a, heaviest first.  Waves w and w + 4 of a block
 // share a SIMD: the i-th heaviest tile is paired with the i-th lightest (slots
 // past the last tile are empty), and the pairs are dealt round-robin over the
 // row blocks, so every block's busiest SIMD carries about the average load.
 void build_sk_tiles(KLayout &kl)
 {
-    const bool wide = kl.KP <= kSmRows * kSmNatWide;
-    const int rows_per_tile = wide ? 16 : kSmRows;
+    const int rows_per_tile = kSmTileRows;
     const int n_tiles = (kl.n_rows + rows_per_tile - 1) / rows_per_tile;
     const int n_rb = (n_tiles + kSmWaves - 1) / kSmWaves;
     const int slots = n_rb * kSmWaves;
@@ -222,31 +221,17 @@ int gather_split(int64_t n)
 // chip, at least two tiles per wave on average; split boundaries balance the
 // tiles' a pairs.
 constexpr int kMfmaTargetBlocks = 1024;
-// Blocks of kSmWaves waves in one round over the 256 CUs: one per CU for the
-// 16-row variant, two per CU (four waves per SIMD) for the 8-row one.  The
-// 16-row kernel runs beside the real-space kernels, and one block per CU left
-// them more of each SIMD: rock salt 32^3 (k_max 20) took 0.218 instead of
-// 0.223 ms per evaluation.  The 8-row kernel (k_max >= 24) needs the second block:
-// 3.4 instead of 2.5 ms alone at 64^3 (k_max 32).  A count between the two
-// leaves some CUs with one block and others with two (98 us at 32^3).
-constexpr int kSkMfmaBlocksPerCu[2] = {2, 1};  // [8-row kernel, 16-row kernel]
-int sk_mfma_target_blocks(const KLayout &kl)
-{
-    return 256 * kSkMfmaBlocksPerCu[kl.KP <= kSmRows * kSmNatWide ? 1 : 0];
-}
-
-// Row blocks of the matrix-core structure factor: 128-row blocks for the wide
-// variant (k_max <= 8 kSmNatWide - 1), 64-row groups otherwise.
-int sk_mfma_row_blocks(const KLayout &kl)
-{
-    if (kl.KP <= kSmRows * kSmNatWide) return (kl.n_rows + 2 * kLanes - 1) / (2 * kLanes);
-    return (int)kl.unit_base.size();
-}
+// Blocks of kSmWaves waves in one round over the 256 CUs: one per CU.  The
+// structure factor runs beside the real-space kernels, and one block per CU
+// left them more of each SIMD: rock salt 32^3 (k_max 20) took 0.218 instead of
+// 0.223 ms per evaluation with two.
+constexpr int kSkMfmaBlocksPerCu = 1;
+int sk_mfma_target_blocks() { return 256 * kSkMfmaBlocksPerCu; }
 
 // Particle chunks the matrix-core structure factor may use (partial-sum capacity).
 int sk_mfma_chunk_cap(const KLayout &kl)
 {
-    return std::max(1, std::min(kMaxChunks, sk_mfma_target_blocks(kl) / sk_mfma_row_blocks(kl)));
+    return std::max(1, std::min(kMaxChunks, sk_mfma_target_blocks() / sk_mfma_row_blocks(kl.n_rows)));
 }
 
 int gather_mfma_split(int64_t n, const KLayout &kl, bool fp64)
@@ -641,7 +626,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->sk_tile_of = carve<int>(cur, z.sk_tile_of);
     p->pr = carve<d4>(cur, z.pr);
     p->graphs = !(params->flags & EWALD_FLAG_NO_GRAPH);
-    p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmRows * kSmNat &&
+    p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmMaxKP &&
                  sk_mfma_particles(p->kl.KP) >= 8;
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
     p->mfma_gather = !(params->flags & EWALD_FLAG_VALU_GATHER) &&
@@ -719,12 +704,11 @@ ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double 
     CellArgs ca{n, L, p->nc, p->ncell};
     RecipArgs ra{n, L, kl.K, kl.KP, kl.n_rows, kl.n_units, kl.n_items, kl.n_units * kQ * kLanes};
     PairArgs pa{n, L, p->nc, p->ncell, p->prm.r_c * p->prm.r_c, p->prm.alpha};
-    const int n_groups = (int)kl.unit_base.size();
     int n_chunks = sk_chunks(n, kl.n_units, p->tile);
     if (p->mfma_sk) {
         // particle chunks of the matrix-core structure factor: fill the chip, at
         // most the partial-sum capacity, at least one staged tile per chunk
-        int64_t c = sk_mfma_target_blocks(kl) / sk_mfma_row_blocks(kl);
+        int64_t c = sk_mfma_target_blocks() / sk_mfma_row_blocks(kl.n_rows);
         c = std::min<int64_t>(c, p->sz.max_chunks);
         c = std::min<int64_t>(c, (n + sk_mfma_particles(kl.KP) - 1) / sk_mfma_particles(kl.KP));
         n_chunks = (int)std::max<int64_t>(c, 1);
@@ -758,7 +742,7 @@ ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double 
         run(ax, KC_PHASE, [&] { return launch_phase<double>(ax, ra, pos, q, p->pr, tx, ty, tz); });
         run(ax, KC_SK, [&] {
             if (p->mfma_sk)
-                return launch_sk_mfma(ax, ra, n_groups, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
+                return launch_sk_mfma(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
                                       p->row_m, p->unit_base, p->sk_tile_of, p->part);
             return launch_sk(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
                              p->part);

@@ -31,6 +31,8 @@ SMALL_CASES = [
     ("k_17", 513, 8.0, 0.8, 2.6, 17),
     ("steep_gaussian_fit_edge", 400, 9.5, 3.0, 4.6, 12),   # sqrt(alpha) r_c = 7.97: FP64 fit near its end
     ("steep_gaussian_library", 400, 9.5, 4.0, 4.2, 12),    # sqrt(alpha) r_c = 8.4: FP64 library erfc
+    ("k_23", 600, 9.0, 1.0, 3.0, 23),                      # 12 pairs of a, KP = 24
+    ("k_24", 600, 9.0, 1.0, 3.0, 24),                      # 13 pairs of a, KP = 32, 32-particle staging
 ]
 
 
