@@ -32,7 +32,9 @@ SMALL_CASES = [
     ("steep_gaussian_fit_edge", 400, 9.5, 3.0, 4.6, 12),   # sqrt(alpha) r_c = 7.97: FP64 fit near its end
     ("steep_gaussian_library", 400, 9.5, 4.0, 4.2, 12),    # sqrt(alpha) r_c = 8.4: FP64 library erfc
     ("k_23", 600, 9.0, 1.0, 3.0, 23),                      # 12 pairs of a, KP = 24
-    ("k_24", 600, 9.0, 1.0, 3.0, 24),                      # 13 pairs of a, KP = 32, 32-particle staging
+    ("k_24", 600, 9.0, 1.0, 3.0, 24),                      # 13 pairs of a, KP = 32
+    ("k_47", 300, 12.0, 1.0, 3.5, 47),                     # 24 pairs of a: the matrix-core limit
+    ("k_48", 300, 12.0, 1.0, 3.5, 48),                     # vector-ALU structure factor beyond it
 ]
 
 
