@@ -102,7 +102,7 @@ template <typename R>
 hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
                         typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
 // lanes per slot in the structure-factor reduction (k_sk_reduce)
-constexpr int kRedSlotLanes = 16;
+constexpr int kRedSlotLanes = 4;
 // structure factor (FP64 phases and sums in both precisions)
 size_t sk_smem_bytes(int ts, int K1);
 int sk_tile(int K1);

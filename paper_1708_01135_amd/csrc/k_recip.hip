@@ -327,10 +327,14 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
 {
     __shared__ double s_e[256];
     const int n_slots = n_units * kQ * kLanes;
-    // kRedLanes lanes per slot: lane c sums chunks c, c + kRedLanes, ...; the
-    // partial sums are then combined by a fixed xor-shuffle tree
-    const int sub = threadIdx.x % kRedLanes;
-    const int slot = blockIdx.x * (256 / kRedLanes) + threadIdx.x / kRedLanes;
+    // kRedLanes lanes per slot: lane group c sums chunks c, c + kRedLanes, ...;
+    // the partial sums are then combined by a fixed xor-shuffle tree.  A wave
+    // takes kLanes / kRedLanes consecutive slots, so every load instruction
+    // reads kRedLanes contiguous runs of slots.
+    constexpr int kWaveSlots = kLanes / kRedLanes;
+    const int ln = (int)threadIdx.x % kLanes;
+    const int sub = ln / kWaveSlots;
+    const int slot = blockIdx.x * (256 / kRedLanes) + ((int)threadIdx.x / kLanes) * kWaveSlots + ln % kWaveSlots;
     const int cslot = slot < n_slots ? slot : n_slots - 1;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int c = sub; c < n_chunks; c += kRedLanes) {
@@ -341,7 +345,7 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
         s3 += p.d;
     }
 #pragma unroll
-    for (int w = 1; w < kRedLanes; w <<= 1) {
+    for (int w = kWaveSlots; w < kLanes; w <<= 1) {
         s0 += __shfl_xor(s0, w);
         s1 += __shfl_xor(s1, w);
         s2 += __shfl_xor(s2, w);
