@@ -54,13 +54,9 @@ int isqrt_floor(int v)
     return r;
 }
 
-// fp64_rows: the FP64 16x16x4 MFMA returns row 4 r + g of its output in lane
-// group g, register r (the FP32 one returns row 4 g + r); the tile rows of a
-// quad's n_y offsets follow the instruction the plan will use, so that lane
-// group g always holds quad g.
 // Tiles of the matrix-core structure factor dealt to (row block, wave).  Tiles
-// (16 rows in the structure-factor order) are
-// sorted by their blocks of a, heaviest first.  Waves w and w + 4 of a block
+// (16 rows in the structure-factor order) are sorted by their pairs of a,
+// heaviest first.  Waves w and w + 4 of a block
 // share a SIMD: the i-th heaviest tile is paired with the i-th lightest (slots
 // past the last tile are empty), and the pairs are dealt round-robin over the
 // row blocks, so every block's busiest SIMD carries about the average load.
@@ -80,6 +76,10 @@ void build_sk_tiles(KLayout &kl)
     }
 }
 
+// fp64_rows: the FP64 16x16x4 MFMA returns row 4 r + g of its output in lane
+// group g, register r (the FP32 one returns row 4 g + r); the tile rows of a
+// quad's n_y offsets follow the instruction the plan will use, so that lane
+// group g always holds quad g.
 void build_klayout(int K, KLayout &kl, bool fp64_rows = false)
 {
     kl.K = K;
