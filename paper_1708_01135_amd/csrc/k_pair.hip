@@ -77,6 +77,16 @@ __device__ inline float erfcx_f32(float x)
     return acc * t;
 }
 
+// a b + c as one three-operand FP64 FMA.  Written out because the compiler
+// otherwise turns a Horner step whose constant lives in a register into a copy
+// of the constant followed by the accumulating two-operand form.
+__device__ inline double fma3_f64(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
 // erfc(x) exp(x^2) for 0 <= x <= kErfcx64XMax in FP64 (polynomial in the centred
 // u of t = 1 / (1 + x / 2), coefficients in erfcx_fit.h); 1/d by the hardware
 // reciprocal and two Newton steps.
@@ -89,7 +99,7 @@ __device__ inline double erfcx_f64(double x)
     const double u = (t - kErfcx64C) * kErfcx64InvH;
     double acc = kErfcx64Q[kErfcx64Degree];
 #pragma unroll
-    for (int i = kErfcx64Degree - 1; i >= 0; --i) acc = fma(acc, u, kErfcx64Q[i]);
+    for (int i = kErfcx64Degree - 1; i >= 0; --i) acc = fma3_f64(acc, u, kErfcx64Q[i]);
     return acc * t;
 }
 
