@@ -66,6 +66,39 @@ __device__ inline float gauss_f32(double r2, const PairConsts &k)
     return __builtin_amdgcn_ldexpf(__builtin_amdgcn_exp2f((float)(a - n)), (int)n);
 }
 
+// a b + c as one three-operand FP64 FMA.  Written out because the compiler
+// otherwise turns a Horner step whose constant lives in a register into a copy
+// of the constant followed by the accumulating two-operand form.
+__device__ inline double fma3_f64(double a, double b, double c)
+{
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+    return d;
+}
+
+// Taylor coefficients ln(2)^k / k! of 2^f = e^(f ln 2).
+constexpr double exp2_taylor(int k)
+{
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c = c * 0.69314718055994530941723212145817657 / (double)i;
+    return c;
+}
+
+// exp(-alpha r^2) in FP64: 2^a with a = -alpha log2(e) r^2 split as n + f, n =
+// rint(a), |f| <= 1/2, and 2^f by its Taylor series to degree 13 (truncation
+// below 1e-17 relative), in three-operand FMAs.
+__device__ inline double gauss_f64(double r2, const PairConsts &k)
+{
+    constexpr int kDeg = 13;
+    const double a = k.nal2 * r2;
+    const double n = __builtin_rint(a);
+    const double f = a - n;
+    double acc = exp2_taylor(kDeg);
+#pragma unroll
+    for (int i = kDeg - 1; i >= 0; --i) acc = fma3_f64(acc, f, exp2_taylor(i));
+    return __builtin_amdgcn_ldexp(acc, (int)n);
+}
+
 // erfc(x) exp(x^2) for x >= 0 in FP32 (polynomial in t = 1 / (1 + x / 2),
 // coefficients in erfcx_fit.h).
 __device__ inline float erfcx_f32(float x)
@@ -75,16 +108,6 @@ __device__ inline float erfcx_f32(float x)
 #pragma unroll
     for (int i = kErfcxDegree - 1; i >= 0; --i) acc = __builtin_fmaf(acc, t, kErfcxP[i]);
     return acc * t;
-}
-
-// a b + c as one three-operand FP64 FMA.  Written out because the compiler
-// otherwise turns a Horner step whose constant lives in a register into a copy
-// of the constant followed by the accumulating two-operand form.
-__device__ inline double fma3_f64(double a, double b, double c)
-{
-    double d;
-    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
-    return d;
 }
 
 // erfc(x) exp(x^2) for 0 <= x <= kErfcx64XMax in FP64 (polynomial in the centred
@@ -128,7 +151,7 @@ __device__ inline void pair_term(double dx, double dy, double dz, double r2, dou
         double ri = __builtin_amdgcn_rsq(r2);
         ri = fma(0.5 * ri, fma(-r2 * ri, ri, 1.0), ri);
         ri = fma(0.5 * ri, fma(-r2 * ri, ri, 1.0), ri);
-        const double e = exp(-k.alpha * r2);
+        const double e = gauss_f64(r2, k);
         const double ec = e * erfcx_f64(k.sa * (r2 * ri)) * ri;
         const double f = qj * (ec + k.tsap * e) * (ri * ri);
         ph += qj * ec;
