@@ -29,8 +29,6 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 constexpr int kGmWaves = 4;
-constexpr int kGmBlocksPerCu = 4;
-constexpr size_t kGmMinLds = 160 * 1024 / (kGmBlocksPerCu + 1) + 256;  // 160 KB of LDS per CU
 
 template <typename R>
 struct Mfma;
@@ -305,12 +303,7 @@ hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, co
                               const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart)
 {
     const int blocks = ceil_div(a.n, mfma_block_particles<R>());
-    size_t smem = gather_mfma_smem_bytes(nap_max, sizeof(R) == 8);
-    // FP32: at most kGmBlocksPerCu blocks per CU (LDS reserved so that one more
-    // does not fit), which leaves the real-space kernels running beside the
-    // gather more of each SIMD: rock salt 32^3 took 0.212 instead of 0.216 ms
-    // per evaluation; larger systems were unchanged.
-    if (sizeof(R) == 4 && smem < kGmMinLds) smem = kGmMinLds;
+    const size_t smem = gather_mfma_smem_bytes(nap_max, sizeof(R) == 8);
     hipLaunchKernelGGL(k_gather_mfma<R>, dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L, a.KP,
                        nap_max, split, pq, tz, tiles, mcoef, gpart);
     return hipGetLastError();
