@@ -296,6 +296,7 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     // time (lane l takes position P0 + l).  Lane l's range is the last one
     // starting at or before its position: its ordinal is the number of range
     // starts in [0, P0 + l], minus one, read off the start-bit map.
+    uint32_t *const list_item = list + (size_t)i0 * cap;  // rows of the item's home particles
     int base = 0;  // range starts before the current chunk
     for (int seg = 0; seg < total; seg += kStreamSeg) {
         __syncthreads();  // the previous segment's map is no longer read
@@ -335,12 +336,17 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
                     const double dx = hx[h] - px, dy = hy[h] - py, dz = hz[h] - pz;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const bool in = (r2 < rc2) & (self != i0 + h);
-                    const uint64_t mk = __builtin_amdgcn_ballot_w64(in);
+                    // the ballots of the two compares (lane masks as they stand),
+                    // not of their combination, which would be rebuilt from a
+                    // per-lane 0/1 value
+                    const uint64_t mk =
+                        __builtin_amdgcn_ballot_w64(r2 < rc2) & __builtin_amdgcn_ballot_w64(self != i0 + h);
                     if (mk != 0) {  // wave-uniform: most chunks hold no pair of most homes
                         int pos = cnt[h] + (int)__builtin_amdgcn_mbcnt_hi(
                                                (unsigned)(mk >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mk, 0u));
                         pos = pos < cap ? pos : cap - 1;  // an overflowing list is not used
-                        if (in) list[(size_t)(i0 + h) * cap + pos] = entry;
+                        // one uniform base for the item's rows plus an unsigned 32-bit offset
+                        if (in) list_item[(unsigned)(h * cap) + (unsigned)pos] = entry;
                         cnt[h] += __popcll(mk);
                     }
                 }
