@@ -104,3 +104,33 @@ def test_fp64_erfc_reconstruction():
     x = np.linspace(0.05, 6.0, 100001)
     rec = np.exp(-x * x) * _eval_fp64(x)
     assert np.max(np.abs(rec / erfc(x) - 1.0)) < 1e-13
+
+
+def _gauss_fp64_split(r2, alpha, degree=13):
+    """exp(-alpha r^2) as the FP64 pair loop forms it: a = -alpha log2(e) r^2,
+    n = rint(a), f = a - n, 2^f by its Taylor series in f ln 2 to `degree`
+    (coefficients (ln 2)^k / k! built by repeated multiplication)."""
+    a = (-alpha * 1.44269504088896340735992468100189214) * r2
+    n = np.rint(a)
+    f = a - n
+    c = [1.0]
+    for k in range(1, degree + 1):
+        c.append(c[-1] * 0.69314718055994530941723212145817657 / k)
+    acc = np.full_like(f, c[degree])
+    for k in range(degree - 1, -1, -1):
+        acc = acc * f + c[k]
+    return np.ldexp(acc, n.astype(np.int64))
+
+
+def test_fp64_gaussian_split_matches_exp():
+    # alpha r^2 over the range the FP64 fit serves (sqrt(alpha) r <= 8)
+    for alpha in (0.5, 0.7, 4.0):
+        r2 = np.linspace(0.0, 64.0 / alpha, 200001)
+        got = _gauss_fp64_split(r2, alpha)
+        ref = np.exp(-alpha * r2)
+        assert np.max(np.abs(got / ref - 1.0)) < 2e-14
+    # degree 13 is what the truncation bound asks for; one term fewer is visibly worse
+    f = np.linspace(-0.5, 0.5, 10001)
+    r2 = -f / (0.7 * 1.44269504088896340735992468100189214)
+    assert np.max(np.abs(_gauss_fp64_split(r2, 0.7) / 2.0 ** f - 1.0)) < 1e-15
+    assert np.max(np.abs(_gauss_fp64_split(r2, 0.7, degree=11) / 2.0 ** f - 1.0)) > 1e-15
