@@ -65,12 +65,13 @@ __global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, i
     C *buf = reinterpret_cast<C *>(smem);  // [rows of the block][KP]
     const int rows = (int)blockDim.x / 2;
     const int lr = (int)threadIdx.x >> 1, h = (int)threadIdx.x & 1;
-    const int64_t total = n * 3;
+    // grid row = axis: a block's rows are consecutive particles of one table,
+    // so its write-out is one contiguous run
+    const int ax = (int)blockIdx.y;
     const int64_t r0 = (int64_t)blockIdx.x * rows;
     const int64_t row = r0 + lr;
-    if (row < total) {
-        const int ax = (int)(row % 3);
-        const int64_t j = row / 3;
+    if (row < n) {
+        const int64_t j = row;
         const double qj = qv[j];
         const double x = wrap_coord(pos[3 * j + ax], L);
         if (ax == 0 && h == 0) {
@@ -105,16 +106,10 @@ __global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, i
         }
     }
     __syncthreads();
-    const int64_t nrows = total - r0 < rows ? total - r0 : rows;
+    const int64_t nrows = n - r0 < rows ? n - r0 : rows;
     const int count = (int)nrows * KP;
-    for (int e = (int)threadIdx.x; e < count; e += (int)blockDim.x) {
-        const int er = e / KP, k = e - er * KP;
-        const int64_t rg = r0 + er;
-        const int ax = (int)(rg % 3);
-        const int64_t j = rg / 3;
-        C *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + j * KP + k;
-        *out = buf[e];
-    }
+    C *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + r0 * KP;
+    for (int e = (int)threadIdx.x; e < count; e += (int)blockDim.x) out[e] = buf[e];
 }
 
 // --------------------------------------------------------------------- k_sk
@@ -553,8 +548,7 @@ hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, co
     // rows per block: kPhaseRows, fewer when their LDS stage would pass 64 KB
     int rows = kPhaseRows;
     while (rows > 1 && (size_t)rows * a.KP * sizeof(typename Cplx<R>::type) > 64 * 1024) rows /= 2;
-    const int64_t total = a.n * 3;
-    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(total, rows)), dim3(2 * rows),
+    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(a.n, rows), 3), dim3(2 * rows),
                        (size_t)rows * a.KP * sizeof(typename Cplx<R>::type), s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
                        tz);
     return hipGetLastError();
