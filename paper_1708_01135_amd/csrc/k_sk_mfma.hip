@@ -28,11 +28,11 @@ namespace {
 
 // One staged sub-chunk against the wave's tile, on the FP64 4x4x4 instruction
 // (four independent 4x4x4 products per instruction, block g = (l / 4) % 4): a
-// wave owns 16 rows and takes the values of a two at a time.  Lane l supplies A = U of row
-// l % 16 (block (l / 4) % 4, A row l % 4) for particle l / 16 of the quad (the
-// K index), and B = component l % 2 of z^(2b + (l % 4) / 2) of the same particle
-// (every block gets the same B); two instructions per quad and pair b, one with
-// Re U and one with Im U.  The output of lane l is row 4 ((l / 4) % 4) + l / 16
+// wave owns 16 rows and takes the values of a two at a time.  Lane l supplies
+// A = U of row l % 16 (block (l / 4) % 4, A row l % 4) for particle l / 16 of
+// the quad (the K index), and B = component l % 2 of z^(2b + (l % 4) / 2) of the
+// same particle (every block gets the same B); two instructions per quad and
+// pair b, one with Re U and one with Im U.  The output of lane l is row 4 ((l / 4) % 4) + l / 16
 // of the tile against column l % 4.  Pairs of a waste at most one column of a
 // row (the 8-wide blocks of the 16x16x4 form wasted 22 % of the (row, a) pairs
 // at k_max = 20), and on this part the 4x4x4 instruction sustains about 1.45x
@@ -79,17 +79,15 @@ __device__ __forceinline__ void sk_tile_dispatch(int nap, const c64 *__restrict_
 // k_max < 2 kSmNapSmall, kSmNap otherwise): fewer accumulators leave more of
 // the SIMD's registers to the real-space kernels that run beside it.
 template <int NMAX>
-__global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int KP, int P, int n_rows,
-                                                                     int n_rblocks, int n_chunks, int chunk_len,
-                                                                     const c64 *__restrict__ tx,
-                                                                     const c64 *__restrict__ ty,
-                                                                     const c64 *__restrict__ tz,
-                                                                     const int *__restrict__ row_nx,
-                                                                     const int *__restrict__ row_ny,
-                                                                     const int *__restrict__ row_m,
-                                                                     const int *__restrict__ unit_base,
-                                                                     const int *__restrict__ tile_of, int n_slots,
-                                                                     d4 *__restrict__ part)
+__global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int KP, int P, int n_rows, int n_rblocks,
+                                                              int n_chunks, int chunk_len, const c64 *__restrict__ tx,
+                                                              const c64 *__restrict__ ty, const c64 *__restrict__ tz,
+                                                              const int *__restrict__ row_nx,
+                                                              const int *__restrict__ row_ny,
+                                                              const int *__restrict__ row_m,
+                                                              const int *__restrict__ unit_base,
+                                                              const int *__restrict__ tile_of, int n_slots,
+                                                              d4 *__restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     c64 *st = reinterpret_cast<c64 *>(smem);  // [3][P][KP]: q x^n, y^n, z^n
