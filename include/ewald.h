@@ -201,6 +201,27 @@ ewald_status ewald_debug_kset(ewald_plan_t plan, int32_t *n_xyz);
  * kcount doubles).  Synchronises the plan's stream. */
 ewald_status ewald_debug_copy_sk(ewald_plan_t plan, double *re, double *im);
 
+/* Which branches of the path the plan takes and took (host values).  Filled
+ * from the plan's parameters and, after synchronising the plan's stream, from
+ * the device state of its last completed evaluation of n particles (n must be
+ * that evaluation's particle count).  For tests of the fallback paths. */
+typedef struct {
+    int64_t max_cell_count;      /* most particles in one real-space cell            */
+    int64_t direct_particles;    /* particles whose neighbour list would have passed
+                                    the capacity, evaluated by the direct loop        */
+    int64_t listed_pairs;        /* ordered pairs (i, j, image) with |d| < r_c found
+                                    by the neighbour lists (direct-loop particles'
+                                    pairs are not counted)                            */
+    int32_t cells_per_axis;      /* real-space cells per axis                         */
+    int32_t list_capacity;       /* neighbour-list entries per particle               */
+    int32_t sk_matrix_cores;     /* 1: structure factor on the matrix cores           */
+    int32_t gather_matrix_cores; /* 1: force gather on the matrix cores               */
+    int32_t phase_rows;          /* table rows per phase-kernel block                 */
+    int32_t reserved;
+} ewald_debug_stats;
+
+ewald_status ewald_debug_stats_read(ewald_plan_t plan, int64_t n, ewald_debug_stats *out);
+
 /* Kernel timing: when enabled, every launch of the plan is bracketed by HIP
  * events on the plan's stream and its duration accumulated per kernel class.
  * ewald_profile_read() synchronises, fills up to max_entries names (static

@@ -52,6 +52,10 @@ def _load():
     lib.oracle_energy_forces.restype = ctypes.c_int
     lib.oracle_energy_forces.argtypes = [ctypes.c_int64, _d, _d, ctypes.c_double, ctypes.c_double,
                                          ctypes.c_double, ctypes.c_int, ctypes.c_int, _d, _d, _d]
+    lib.oracle_energy_forces_targets.restype = ctypes.c_int
+    lib.oracle_energy_forces_targets.argtypes = [ctypes.c_int64, _d, _d, ctypes.c_double, ctypes.c_double,
+                                                 ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                                 _i64, _d, _d, _d, _d, _d]
     lib.oracle_num_threads.restype = ctypes.c_int
     lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -145,4 +149,30 @@ def energy_forces(pos, q, box_L, alpha, r_c, k_max, method=FAST) -> Tuple[np.nda
     dq = np.zeros(n)
     _check(_load().oracle_energy_forces(n, _p(pos), _p(q), box_L, alpha, r_c, int(k_max), int(method),
                                         _p(en), _p(f), _p(dq)), "energy_forces")
+    return en, f, dq
+
+
+def energy_forces_targets(pos, q, box_L, alpha, r_c, k_max, targets=None, method=FAST, want_sk=False):
+    """(energy[5], forces (nt,3), dE/dq (nt,)[, S_k over the half space in kset() order]) with the
+    per-particle results of the listed targets only (all particles when ``targets`` is None).
+
+    Every value is assembled inside the C oracle: the real-space sums run over all
+    particles (E_real needs every phi_i), the reciprocal forces and potentials over the
+    targets."""
+    pos, q = _f64(pos), _f64(q)
+    tg = None if targets is None else np.ascontiguousarray(np.asarray(targets, dtype=np.int64))
+    nt = len(q) if tg is None else len(tg)
+    en = np.zeros(5)
+    f = np.zeros((nt, 3))
+    dq = np.zeros(nt)
+    skr = ski = None
+    if want_sk:
+        nk = len(kset(k_max, True))
+        skr, ski = np.zeros(nk), np.zeros(nk)
+    _check(_load().oracle_energy_forces_targets(len(q), _p(pos), _p(q), box_L, alpha, r_c, int(k_max),
+                                                int(method), 0 if tg is None else len(tg), _p(tg, _i64),
+                                                _p(en), _p(f), _p(dq), _p(skr), _p(ski)),
+           "energy_forces_targets")
+    if want_sk:
+        return en, f, dq, skr + 1j * ski
     return en, f, dq

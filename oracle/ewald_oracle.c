@@ -495,3 +495,58 @@ int oracle_energy_forces(int64_t n, const double *pos, const double *q, double L
     free(pk);
     return 0;
 }
+
+/* Same quantities as oracle_energy_forces, with the per-particle outputs
+ * restricted to a list of targets (all particles when targets == NULL):
+ *   energy[5]      total, real, reciprocal, self, background (all particles)
+ *   forces[t][3]   F_i = F_real,i + F_recip,i of particle i = targets[t]
+ *   dEdq[t]        phi_real,i + phi_recip,i - 2 sqrt(alpha/pi) q_i - pi Q / (V alpha)
+ *   sk_re, sk_im   optional half-space S_k in oracle_kset(k_max, 1) order
+ *                  (table route only)
+ * The real-space part is evaluated for every particle (E_real needs every
+ * phi_i); the reciprocal forces and potentials only for the targets. */
+int oracle_energy_forces_targets(int64_t n, const double *pos, const double *q, double L, double alpha,
+                                 double r_c, int k_max, int method, int64_t n_targets,
+                                 const int64_t *targets, double *energy, double *forces, double *dEdq,
+                                 double *sk_re, double *sk_im)
+{
+    if (n < 1 || !pos || !q || !energy) return -1;
+    if ((sk_re || sk_im) && method == ORACLE_BRUTE) return -1;
+    const int64_t nt = targets ? n_targets : n;
+    if (nt < 0) return -1;
+    for (int64_t t = 0; targets && t < nt; ++t)
+        if (targets[t] < 0 || targets[t] >= n) return -1;
+    double *fr = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+    double *pr = (double *)malloc(sizeof(double) * (size_t)n);
+    double *fk = (double *)malloc(sizeof(double) * 3 * (size_t)(nt > 0 ? nt : 1));
+    double *pk = (double *)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+    if (!fr || !fk || !pr || !pk) { free(fr); free(fk); free(pr); free(pk); return -3; }
+    double er = 0, ek = 0;
+    int st = oracle_real_space(n, pos, q, L, alpha, r_c, method, 0, NULL, &er, fr, pr);
+    if (st == 0)
+        st = oracle_recip_space(n, pos, q, L, alpha, k_max, method, nt, targets, &ek, fk, pk, sk_re, sk_im);
+    if (st != 0) { free(fr); free(fk); free(pr); free(pk); return st; }
+    double q2 = 0, Q = 0;
+    for (int64_t i = 0; i < n; ++i) { q2 += q[i] * q[i]; Q += q[i]; }
+    const double V = L * L * L;
+    const double es = -sqrt(alpha / ORACLE_PI) * q2;
+    const double eb = -ORACLE_PI * Q * Q / (2.0 * V * alpha);
+    energy[1] = er;
+    energy[2] = ek;
+    energy[3] = es;
+    energy[4] = eb;
+    energy[0] = er + ek + es + eb;
+    const double c_self = 2.0 * sqrt(alpha / ORACLE_PI);
+    const double c_bg = ORACLE_PI * Q / (V * alpha);
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t i = targets ? targets[t] : t;
+        if (forces)
+            for (int a = 0; a < 3; ++a) forces[3 * t + a] = fr[3 * i + a] + fk[3 * t + a];
+        if (dEdq) dEdq[t] = pr[i] + pk[t] - c_self * q[i] - c_bg;
+    }
+    free(fr);
+    free(fk);
+    free(pr);
+    free(pk);
+    return 0;
+}

@@ -101,6 +101,9 @@ struct RecipArgs {
 template <typename R>
 hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
                         typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz);
+// table rows per phase block for a KP (fewer when the LDS stage would pass 64 KB)
+template <typename R>
+int phase_rows(int KP);
 // lanes per slot in the structure-factor reduction (k_sk_reduce)
 constexpr int kRedSlotLanes = 4;
 // structure factor (FP64 phases and sums in both precisions)

@@ -542,12 +542,19 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, Spl
 }  // namespace
 
 template <typename R>
-hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
-                        typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz)
+int phase_rows(int KP)
 {
     // rows per block: kPhaseRows, fewer when their LDS stage would pass 64 KB
     int rows = kPhaseRows;
-    while (rows > 1 && (size_t)rows * a.KP * sizeof(typename Cplx<R>::type) > 64 * 1024) rows /= 2;
+    while (rows > 1 && (size_t)rows * KP * sizeof(typename Cplx<R>::type) > 64 * 1024) rows /= 2;
+    return rows;
+}
+
+template <typename R>
+hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, const double *q, d4 *pr,
+                        typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz)
+{
+    const int rows = phase_rows<R>(a.KP);
     hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(a.n, rows), 3), dim3(2 * rows),
                        (size_t)rows * a.KP * sizeof(typename Cplx<R>::type), s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
                        tz);
@@ -606,6 +613,7 @@ hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const S
 }
 
 #define EWK_INSTANTIATE(R)                                                                                         \
+    template int phase_rows<R>(int);                                                                               \
     template hipError_t launch_phase<R>(hipStream_t, const RecipArgs &, const double *, const double *, d4 *,     \
                                         Cplx<R>::type *, Cplx<R>::type *, Cplx<R>::type *);                        \
     template hipError_t launch_sk_reduce<R>(hipStream_t, const RecipArgs &, int, const d4 *, const int *,          \

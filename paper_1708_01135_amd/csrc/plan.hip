@@ -258,7 +258,10 @@ void mfma_split_table(const KLayout &kl, int n_split, SplitTable &st)
 
 size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Sizes of every device buffer; shared by the admission query and the plan.
+// Sizes of every device buffer; shared by the admission query, the plan and
+// the static-scratch evaluation.  "Tables" are the plan's constants and its
+// status word; the "work" buffers are what one evaluation of up to N particles
+// writes and reads.
 struct Sizes {
     size_t cell_of, counts, fill, cell_start, tmp_idx, perm, status;
     size_t pq, freal, qpart, scalars, epart, erec, ck;
@@ -266,7 +269,7 @@ struct Sizes {
     size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
     size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
     size_t mcoef, mtiles, row_mbase, unit_base, sk_tile_of, pr;
-    size_t total;
+    size_t tables, work, total;
     int max_chunks;
     int max_pitems;  // pair work items: cells + n/kPairHome bounds sum_c ceil(count_c / kPairHome)
     int list_cap;    // neighbour-list entries per particle
@@ -283,10 +286,11 @@ int pair_list_cap(const ewald_params &p)
     return (int)std::min(cap, 60000.0);
 }
 
-void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
+// N: particles the work buffers are sized for (n_max for a plan's own
+// workspace, the call's n for the static scratch).
+void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, int64_t N, Sizes &z)
 {
     const bool mixed = p.precision == EWALD_PRECISION_MIXED;
-    const int64_t N = p.n_max;
     const size_t ncell = (size_t)nc * nc * nc;
     const size_t creal = sizeof(c64);  // phase tables are FP64 in both precisions
     const size_t real = mixed ? sizeof(float) : sizeof(double);
@@ -329,9 +333,67 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, Sizes &z)
     z.unit_base = align_up(sizeof(int) * kl.unit_base.size());
     z.sk_tile_of = align_up(sizeof(int) * kl.sk_tile_of.size());
     z.pr = align_up(sizeof(d4) * N);
-    z.total = z.pr + z.mcoef + z.mtiles + z.row_mbase + z.unit_base + z.sk_tile_of + 2 * z.pitem_cell + z.n_pitems + z.plist + z.plist_cnt + z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.status + z.pq + z.freal +
-              z.qpart + z.scalars + z.epart + z.erec + z.ck + 3 * z.tx + z.part + z.sk + z.rec + z.gpart +
-              3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx;
+    z.tables = z.status + z.ck + 3 * z.row_nx + 2 * z.unit_g + z.row_item + 3 * z.item_nx + z.mtiles + z.row_mbase +
+               z.unit_base + z.sk_tile_of;
+    z.work = z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.pq + z.freal + z.qpart +
+             z.scalars + z.epart + z.erec + 3 * z.tx + z.part + z.sk + z.rec + z.gpart + 2 * z.pitem_cell +
+             z.n_pitems + z.plist + z.plist_cnt + z.mcoef + z.pr;
+    z.total = z.tables + z.work;
+}
+
+// Per-evaluation buffers, carved from the plan's allocation or from the
+// static scratch.
+struct Work {
+    int *cell_of = nullptr, *counts = nullptr, *fill = nullptr, *cell_start = nullptr, *tmp_idx = nullptr,
+        *perm = nullptr;
+    d4 *pq = nullptr, *freal = nullptr, *part = nullptr, *sk = nullptr, *gpart = nullptr;
+    double *qpart = nullptr, *scalars = nullptr, *epart = nullptr, *erec = nullptr;
+    void *tx = nullptr, *ty = nullptr, *tz = nullptr, *rec = nullptr;
+    int *pitem_cell = nullptr, *pitem_off = nullptr, *n_pitems = nullptr, *plist_cnt = nullptr;
+    uint32_t *plist = nullptr;
+    void *mcoef = nullptr;
+    d4 *pr = nullptr;  // caller-order particle records of the reciprocal kernels
+    int max_chunks = 1, list_cap = 1;
+};
+
+template <typename T>
+T *carve(char *&cur, size_t bytes)
+{
+    T *r = reinterpret_cast<T *>(cur);
+    cur += bytes;
+    return r;
+}
+
+void carve_work(char *cur, const Sizes &z, Work &w)
+{
+    w.cell_of = carve<int>(cur, z.cell_of);
+    w.counts = carve<int>(cur, z.counts);
+    w.fill = carve<int>(cur, z.fill);
+    w.cell_start = carve<int>(cur, z.cell_start);
+    w.tmp_idx = carve<int>(cur, z.tmp_idx);
+    w.perm = carve<int>(cur, z.perm);
+    w.pq = carve<d4>(cur, z.pq);
+    w.freal = carve<d4>(cur, z.freal);
+    w.qpart = carve<double>(cur, z.qpart);
+    w.scalars = carve<double>(cur, z.scalars);
+    w.epart = carve<double>(cur, z.epart);
+    w.erec = carve<double>(cur, z.erec);
+    w.tx = carve<void>(cur, z.tx);
+    w.ty = carve<void>(cur, z.tx);
+    w.tz = carve<void>(cur, z.tx);
+    w.part = carve<d4>(cur, z.part);
+    w.sk = carve<d4>(cur, z.sk);
+    w.rec = carve<void>(cur, z.rec);
+    w.gpart = carve<d4>(cur, z.gpart);
+    w.pitem_cell = carve<int>(cur, z.pitem_cell);
+    w.pitem_off = carve<int>(cur, z.pitem_off);
+    w.n_pitems = carve<int>(cur, z.n_pitems);
+    w.plist = carve<uint32_t>(cur, z.plist);
+    w.plist_cnt = carve<int>(cur, z.plist_cnt);
+    w.mcoef = carve<void>(cur, z.mcoef);
+    w.pr = carve<d4>(cur, z.pr);
+    w.max_chunks = z.max_chunks;
+    w.list_cap = z.list_cap;
 }
 
 struct ProfRec {
@@ -357,22 +419,18 @@ struct ewald_plan_s {
     KLayout kl;
     Sizes sz{};
     void *base = nullptr;
-    // device views
-    int *cell_of = nullptr, *counts = nullptr, *fill = nullptr, *cell_start = nullptr, *tmp_idx = nullptr,
-        *perm = nullptr, *status = nullptr;
-    d4 *pq = nullptr, *freal = nullptr, *part = nullptr, *sk = nullptr, *gpart = nullptr;
-    double *qpart = nullptr, *scalars = nullptr, *epart = nullptr, *erec = nullptr, *ck = nullptr;
-    void *tx = nullptr, *ty = nullptr, *tz = nullptr, *rec = nullptr;
+    bool has_work = true;  // false: EWALD_FLAG_NO_WORKSPACE (tables only)
+    // plan-resident tables and status word
+    int *status = nullptr;
+    double *ck = nullptr;
     int *row_nx = nullptr, *row_ny = nullptr, *row_m = nullptr, *unit_g = nullptr, *unit_s = nullptr,
         *row_item = nullptr, *item_nx = nullptr, *item_ny = nullptr, *item_seg = nullptr;
-    int *pitem_cell = nullptr, *pitem_off = nullptr, *n_pitems = nullptr, *plist_cnt = nullptr;
-    uint32_t *plist = nullptr;
-    void *mcoef = nullptr;
     MTile *mtiles = nullptr;
     int *row_mbase = nullptr;
     int *unit_base = nullptr;
     int *sk_tile_of = nullptr;
-    d4 *pr = nullptr;  // caller-order particle records of the reciprocal kernels
+    // the plan's own per-evaluation buffers (empty without a workspace)
+    Work w;
     bool mfma_gather = false, mfma_sk = false;
     // graph replay of repeated evaluations (same n, buffers and kind)
     struct GraphKey {
@@ -465,14 +523,6 @@ void drain_profile(ewald_plan_s *p)
 }
 
 template <typename T>
-T *carve(char *&cur, size_t bytes)
-{
-    T *r = reinterpret_cast<T *>(cur);
-    cur += bytes;
-    return r;
-}
-
-template <typename T>
 hipError_t upload(T *dst, const std::vector<T> &src, hipStream_t s)
 {
     if (src.empty()) return hipSuccess;
@@ -532,7 +582,7 @@ size_t ewald_plan_workspace_bytes(const ewald_params *p)
     KLayout kl;
     build_klayout(p->k_max, kl);
     Sizes z;
-    compute_sizes(*p, kl, cells_per_axis(p->box_L, p->r_c), z);
+    compute_sizes(*p, kl, cells_per_axis(p->box_L, p->r_c), p->n_max, z);
     return z.total;
 }
 
@@ -551,7 +601,8 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->ncell = p->nc * p->nc * p->nc;
     build_klayout(params->k_max, p->kl, !p->mixed);
     p->tile = sk_tile(params->k_max + 1);
-    compute_sizes(*params, p->kl, p->nc, p->sz);
+    p->has_work = true;
+    compute_sizes(*params, p->kl, p->nc, params->n_max, p->sz);
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || params->device >= ndev) {
@@ -563,7 +614,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
         delete p;
         return EWALD_ERR_DEVICE;
     }
-    if (hipMalloc(&p->base, p->sz.total) != hipSuccess) {
+    if (hipMalloc(&p->base, p->has_work ? p->sz.total : p->sz.tables) != hipSuccess) {
         (void)hipGetLastError();
         delete p;
         return EWALD_ERR_OUT_OF_MEMORY;
@@ -584,27 +635,8 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     }
     char *cur = static_cast<char *>(p->base);
     const Sizes &z = p->sz;
-    p->cell_of = carve<int>(cur, z.cell_of);
-    p->counts = carve<int>(cur, z.counts);
-    p->fill = carve<int>(cur, z.fill);
-    p->cell_start = carve<int>(cur, z.cell_start);
-    p->tmp_idx = carve<int>(cur, z.tmp_idx);
-    p->perm = carve<int>(cur, z.perm);
     p->status = carve<int>(cur, z.status);
-    p->pq = carve<d4>(cur, z.pq);
-    p->freal = carve<d4>(cur, z.freal);
-    p->qpart = carve<double>(cur, z.qpart);
-    p->scalars = carve<double>(cur, z.scalars);
-    p->epart = carve<double>(cur, z.epart);
-    p->erec = carve<double>(cur, z.erec);
     p->ck = carve<double>(cur, z.ck);
-    p->tx = carve<void>(cur, z.tx);
-    p->ty = carve<void>(cur, z.tx);
-    p->tz = carve<void>(cur, z.tx);
-    p->part = carve<d4>(cur, z.part);
-    p->sk = carve<d4>(cur, z.sk);
-    p->rec = carve<void>(cur, z.rec);
-    p->gpart = carve<d4>(cur, z.gpart);
     p->row_nx = carve<int>(cur, z.row_nx);
     p->row_ny = carve<int>(cur, z.row_ny);
     p->row_m = carve<int>(cur, z.row_m);
@@ -614,17 +646,11 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->item_nx = carve<int>(cur, z.item_nx);
     p->item_ny = carve<int>(cur, z.item_ny);
     p->item_seg = carve<int>(cur, z.item_seg);
-    p->pitem_cell = carve<int>(cur, z.pitem_cell);
-    p->pitem_off = carve<int>(cur, z.pitem_off);
-    p->n_pitems = carve<int>(cur, z.n_pitems);
-    p->plist = carve<uint32_t>(cur, z.plist);
-    p->plist_cnt = carve<int>(cur, z.plist_cnt);
-    p->mcoef = carve<void>(cur, z.mcoef);
     p->mtiles = carve<MTile>(cur, z.mtiles);
     p->row_mbase = carve<int>(cur, z.row_mbase);
     p->unit_base = carve<int>(cur, z.unit_base);
     p->sk_tile_of = carve<int>(cur, z.sk_tile_of);
-    p->pr = carve<d4>(cur, z.pr);
+    if (p->has_work) carve_work(cur, z, p->w);
     p->graphs = !(params->flags & EWALD_FLAG_NO_GRAPH);
     p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmMaxKP &&
                  sk_mfma_particles(p->kl.KP) >= 8;
@@ -657,13 +683,15 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (e == hipSuccess) e = upload(p->row_mbase, kl.row_mbase, s);
     if (e == hipSuccess) e = upload(p->unit_base, kl.unit_base, s);
     if (e == hipSuccess) e = upload(p->sk_tile_of, kl.sk_tile_of, s);
-    // padding entries of the tile coefficients are never written and stay zero
-    if (e == hipSuccess) e = hipMemsetAsync(p->mcoef, 0, z.mcoef, s);
-    // counters start at zero; afterwards every evaluation leaves them cleared
-    if (e == hipSuccess) e = hipMemsetAsync(p->counts, 0, z.counts, s);
-    if (e == hipSuccess) e = hipMemsetAsync(p->fill, 0, z.fill, s);
     if (e == hipSuccess) e = hipMemsetAsync(p->status, 0, z.status, s);
-    if (e == hipSuccess) e = hipMemsetAsync(p->sk, 0, z.sk, s);
+    if (p->has_work) {
+        // padding entries of the tile coefficients are never written and stay zero
+        if (e == hipSuccess) e = hipMemsetAsync(p->w.mcoef, 0, z.mcoef, s);
+        // counters start at zero; afterwards every evaluation leaves them cleared
+        if (e == hipSuccess) e = hipMemsetAsync(p->w.counts, 0, z.counts, s);
+        if (e == hipSuccess) e = hipMemsetAsync(p->w.fill, 0, z.fill, s);
+        if (e == hipSuccess) e = hipMemsetAsync(p->w.sk, 0, z.sk, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -695,8 +723,9 @@ namespace {
 // stream while a graph is recorded).  energy_only skips the force gather (the
 // reciprocal energy comes from the structure factor alone); gscale, when
 // given, turns the force / dE/dq outputs into the adjoint.
-ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double *pos, const double *q,
-                         double *energy, double *forces, double *dEdq, const double *gscale, bool energy_only)
+ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_stream, int64_t n,
+                         const double *pos, const double *q, double *energy, double *forces, double *dEdq,
+                         const double *gscale, bool energy_only)
 {
     const KLayout &kl = p->kl;
     const double L = p->prm.box_L;
@@ -709,7 +738,7 @@ ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double 
         // particle chunks of the matrix-core structure factor: fill the chip, at
         // most the partial-sum capacity, at least one staged tile per chunk
         int64_t c = sk_mfma_target_blocks() / sk_mfma_row_blocks(kl.n_rows);
-        c = std::min<int64_t>(c, p->sz.max_chunks);
+        c = std::min<int64_t>(c, w.max_chunks);
         c = std::min<int64_t>(c, (n + sk_mfma_particles(kl.KP) - 1) / sk_mfma_particles(kl.KP));
         n_chunks = (int)std::max<int64_t>(c, 1);
     }
@@ -734,76 +763,79 @@ ewald_status launch_path(ewald_plan_t p, hipStream_t s, int64_t n, const double 
     // (FP32 phase rounding leaves ~1e-5 relative error in S_k of near-lattice
     // systems at small k); the mixed path rounds phases and coefficients to
     // FP32 in the gather and evaluates the pair functions in FP32.
-    hipStream_t ax = p->aux;
-    if (e == hipSuccess) e = hipEventRecord(p->ev_fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(ax, p->ev_fork, 0);
+    // one_stream: everything in order on s (no fork, no events)
+    hipStream_t ax = one_stream ? s : p->aux;
+    if (!one_stream) {
+        if (e == hipSuccess) e = hipEventRecord(p->ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(ax, p->ev_fork, 0);
+    }
     {
-        auto *tx = static_cast<c64 *>(p->tx), *ty = static_cast<c64 *>(p->ty), *tz = static_cast<c64 *>(p->tz);
-        run(ax, KC_PHASE, [&] { return launch_phase<double>(ax, ra, pos, q, p->pr, tx, ty, tz); });
+        auto *tx = static_cast<c64 *>(w.tx), *ty = static_cast<c64 *>(w.ty), *tz = static_cast<c64 *>(w.tz);
+        run(ax, KC_PHASE, [&] { return launch_phase<double>(ax, ra, pos, q, w.pr, tx, ty, tz); });
         run(ax, KC_SK, [&] {
             if (p->mfma_sk)
                 return launch_sk_mfma(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
-                                      p->row_m, p->unit_base, p->sk_tile_of, p->part);
+                                      p->row_m, p->unit_base, p->sk_tile_of, w.part);
             return launch_sk(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
-                             p->part);
+                             w.part);
         });
         if (p->mixed) {
-            float *rec = p->mfma_gather ? nullptr : static_cast<float *>(p->rec);
-            float *mc = p->mfma_gather ? static_cast<float *>(p->mcoef) : nullptr;
+            float *rec = p->mfma_gather ? nullptr : static_cast<float *>(w.rec);
+            float *mc = p->mfma_gather ? static_cast<float *>(w.mcoef) : nullptr;
             run(ax, KC_SKREDUCE, [&] {
-                return launch_sk_reduce<float>(ax, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
-                                               p->row_ny, p->row_m, p->row_item, p->ck, p->sk, rec, mc,
-                                               p->row_mbase, p->erec);
+                return launch_sk_reduce<float>(ax, ra, n_chunks, w.part, p->unit_g, p->unit_s, p->row_nx,
+                                               p->row_ny, p->row_m, p->row_item, p->ck, w.sk, rec, mc,
+                                               p->row_mbase, w.erec);
             });
             if (!energy_only) run(ax, KC_GATHER, [&] {
                 if (p->mfma_gather)
-                    return launch_gather_mfma<float>(ax, ra, n_split, st, kl.nap_max, p->pr, tz, p->mtiles, mc,
-                                                     p->gpart);
-                return launch_gather<float>(ax, ra, n_split, st, p->pr, tz, p->item_seg, rec, p->gpart);
+                    return launch_gather_mfma<float>(ax, ra, n_split, st, kl.nap_max, w.pr, tz, p->mtiles, mc,
+                                                     w.gpart);
+                return launch_gather<float>(ax, ra, n_split, st, w.pr, tz, p->item_seg, rec, w.gpart);
             });
         } else {
-            double *rec = p->mfma_gather ? nullptr : static_cast<double *>(p->rec);
-            double *mc = p->mfma_gather ? static_cast<double *>(p->mcoef) : nullptr;
+            double *rec = p->mfma_gather ? nullptr : static_cast<double *>(w.rec);
+            double *mc = p->mfma_gather ? static_cast<double *>(w.mcoef) : nullptr;
             run(ax, KC_SKREDUCE, [&] {
-                return launch_sk_reduce<double>(ax, ra, n_chunks, p->part, p->unit_g, p->unit_s, p->row_nx,
-                                                p->row_ny, p->row_m, p->row_item, p->ck, p->sk, rec, mc,
-                                                p->row_mbase, p->erec);
+                return launch_sk_reduce<double>(ax, ra, n_chunks, w.part, p->unit_g, p->unit_s, p->row_nx,
+                                                p->row_ny, p->row_m, p->row_item, p->ck, w.sk, rec, mc,
+                                                p->row_mbase, w.erec);
             });
             if (!energy_only) run(ax, KC_GATHER, [&] {
                 if (p->mfma_gather)
-                    return launch_gather_mfma<double>(ax, ra, n_split, st, kl.nap_max, p->pr, tz, p->mtiles, mc,
-                                                      p->gpart);
-                return launch_gather<double>(ax, ra, n_split, st, p->pr, tz, p->item_seg, rec, p->gpart);
+                    return launch_gather_mfma<double>(ax, ra, n_split, st, kl.nap_max, w.pr, tz, p->mtiles, mc,
+                                                      w.gpart);
+                return launch_gather<double>(ax, ra, n_split, st, w.pr, tz, p->item_seg, rec, w.gpart);
             });
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(p->ev_join, ax);
+    if (!one_stream && e == hipSuccess) e = hipEventRecord(p->ev_join, ax);
 
     // Real space on the caller's stream.
-    run(s, KC_BIN, [&] { return launch_bin(s, ca, pos, q, p->cell_of, p->counts, p->qpart, p->status); });
+    run(s, KC_BIN, [&] { return launch_bin(s, ca, pos, q, w.cell_of, w.counts, w.qpart, p->status); });
     run(s, KC_SCAN, [&] {
-        return launch_scan(s, ca, p->counts, p->fill, p->cell_start, p->qpart, nqb, p->scalars, p->pitem_cell,
-                           p->pitem_off, p->n_pitems);
+        return launch_scan(s, ca, w.counts, w.fill, w.cell_start, w.qpart, nqb, w.scalars, w.pitem_cell,
+                           w.pitem_off, w.n_pitems);
     });
-    run(s, KC_SCATTER, [&] { return launch_scatter(s, ca, p->cell_of, p->cell_start, p->fill, p->tmp_idx); });
-    run(s, KC_CELLSORT, [&] { return launch_cellsort(s, ca, p->cell_start, p->tmp_idx, pos, q, p->perm, p->pq); });
+    run(s, KC_SCATTER, [&] { return launch_scatter(s, ca, w.cell_of, w.cell_start, w.fill, w.tmp_idx); });
+    run(s, KC_CELLSORT, [&] { return launch_cellsort(s, ca, w.cell_start, w.tmp_idx, pos, q, w.perm, w.pq); });
     const int max_pitems = p->ncell + ceil_div(n, kPairHome);
     run(s, KC_PAIRLIST, [&] {
-        return launch_pair_list(s, pa, max_pitems, p->n_pitems, p->pitem_cell, p->pitem_off, p->cell_start, p->pq,
-                                p->plist, p->plist_cnt, p->sz.list_cap);
+        return launch_pair_list(s, pa, max_pitems, w.n_pitems, w.pitem_cell, w.pitem_off, w.cell_start, w.pq,
+                                w.plist, w.plist_cnt, w.list_cap);
     });
     run(s, KC_PAIR, [&] {
-        return launch_pair(s, pa, p->mixed, p->cell_start, p->pq, p->plist, p->plist_cnt, p->sz.list_cap, p->freal);
+        return launch_pair(s, pa, p->mixed, w.cell_start, w.pq, w.plist, w.plist_cnt, w.list_cap, w.freal);
     });
 
     // Join, then the totals.
-    if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
+    if (!one_stream && e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
     run(s, KC_FINAL_P, [&] {
-        return launch_finalize_particles(s, fa, p->pq, p->perm, p->freal, p->gpart, p->scalars, forces, dEdq,
-                                         p->epart);
+        return launch_finalize_particles(s, fa, w.pq, w.perm, w.freal, w.gpart, w.scalars, forces, dEdq,
+                                         w.epart);
     });
     run(s, KC_FINAL_E, [&] {
-        return launch_finalize_energy(s, fa, p->epart, ceil_div(n, 256), p->erec, p->scalars, p->status, energy);
+        return launch_finalize_energy(s, fa, w.epart, ceil_div(n, 256), w.erec, w.scalars, p->status, energy);
     });
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -823,7 +855,7 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
     DeviceGuard dg(p->device);
     if (!dg.ok()) return EWALD_ERR_DEVICE;
-    if (p->prof || !p->graphs) return launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+    if (p->prof || !p->graphs) return launch_path(p, p->w, p->stream, false, n, pos, q, energy, forces, dEdq, gscale, energy_only);
     ewald_plan_s::GraphKey key;
     key.n = n;
     key.pos = pos;
@@ -839,7 +871,7 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     // to the eager path, so back-to-back evaluations keep their packet stream.
     auto eager = [&]() {
         p->last_graph = false;
-        return launch_path(p, p->stream, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+        return launch_path(p, p->w, p->stream, false, n, pos, q, energy, forces, dEdq, gscale, energy_only);
     };
     auto graph = [&](hipGraphExec_t x) {
         p->last_graph = true;
@@ -885,7 +917,7 @@ ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double
     hipGraphExec_t x = nullptr;
     ewald_status st = EWALD_ERR_DEVICE;
     if (hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
-        st = launch_path(p, p->cap, n, pos, q, energy, forces, dEdq, gscale, energy_only);
+        st = launch_path(p, p->w, p->cap, false, n, pos, q, energy, forces, dEdq, gscale, energy_only);
         const hipError_t ec = hipStreamEndCapture(p->cap, &g);
         if (ec != hipSuccess || !g) st = EWALD_ERR_DEVICE;
         if (st == EWALD_OK && hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
@@ -1018,7 +1050,7 @@ ewald_status ewald_debug_copy_sk(ewald_plan_t p, double *re, double *im)
     const int n_slots = p->kl.n_units * kQ * kLanes;
     std::vector<d4> h((size_t)n_slots);
     if (hipStreamSynchronize(p->stream) != hipSuccess) return EWALD_ERR_DEVICE;
-    if (hipMemcpy(h.data(), p->sk, sizeof(d4) * n_slots, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpy(h.data(), p->w.sk, sizeof(d4) * n_slots, hipMemcpyDeviceToHost) != hipSuccess)
         return EWALD_ERR_DEVICE;
     std::vector<int> kv;
     std::vector<int64_t> src;
@@ -1028,6 +1060,30 @@ ewald_status ewald_debug_copy_sk(ewald_plan_t p, double *re, double *im)
         re[i] = (src[i] & 1) ? v.c : v.a;
         im[i] = (src[i] & 1) ? v.d : v.b;
     }
+    return EWALD_OK;
+}
+
+ewald_status ewald_debug_stats_read(ewald_plan_t p, int64_t n, ewald_debug_stats *out)
+{
+    if (!p || !out || n < 1 || n > p->prm.n_max) return EWALD_ERR_INVALID_ARG;
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    std::vector<int> cs((size_t)p->ncell + 1), cnt((size_t)n);
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return EWALD_ERR_DEVICE;
+    if (hipMemcpy(cs.data(), p->w.cell_start, sizeof(int) * cs.size(), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(cnt.data(), p->w.plist_cnt, sizeof(int) * cnt.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return EWALD_ERR_DEVICE;
+    std::memset(out, 0, sizeof(*out));
+    for (int c = 0; c < p->ncell; ++c) out->max_cell_count = std::max<int64_t>(out->max_cell_count, cs[c + 1] - cs[c]);
+    for (int v : cnt) {
+        out->direct_particles += v < 0;
+        out->listed_pairs += v > 0 ? v : 0;
+    }
+    out->cells_per_axis = p->nc;
+    out->list_capacity = p->sz.list_cap;
+    out->sk_matrix_cores = p->mfma_sk;
+    out->gather_matrix_cores = p->mfma_gather;
+    out->phase_rows = phase_rows<double>(p->kl.KP);
     return EWALD_OK;
 }
 

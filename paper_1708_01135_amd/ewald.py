@@ -55,6 +55,13 @@ class ServerStats(ctypes.Structure):
                 ("in_flight", ctypes.c_int64), ("budget", ctypes.c_uint64), ("used", ctypes.c_uint64)]
 
 
+class DebugStats(ctypes.Structure):
+    _fields_ = [("max_cell_count", ctypes.c_int64), ("direct_particles", ctypes.c_int64),
+                ("listed_pairs", ctypes.c_int64), ("cells_per_axis", ctypes.c_int32), ("list_capacity", ctypes.c_int32),
+                ("sk_matrix_cores", ctypes.c_int32), ("gather_matrix_cores", ctypes.c_int32),
+                ("phase_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -102,6 +109,8 @@ def _load():
     lib.ewald_debug_kset.argtypes = [vp, vp]
     lib.ewald_debug_copy_sk.restype = ctypes.c_int
     lib.ewald_debug_copy_sk.argtypes = [vp, vp, vp]
+    lib.ewald_debug_stats_read.restype = ctypes.c_int
+    lib.ewald_debug_stats_read.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(DebugStats)]
     lib.ewald_profile_enable.restype = ctypes.c_int
     lib.ewald_profile_enable.argtypes = [vp, ctypes.c_int32]
     lib.ewald_profile_read.restype = ctypes.c_int32
@@ -280,6 +289,14 @@ class Plan:
         if st != OK:
             raise EwaldError(st, "ewald_debug_copy_sk")
         return re + 1j * im
+
+    def debug_stats(self, n: int) -> Dict[str, int]:
+        """Branches the plan takes, and those its last evaluation of ``n`` particles took."""
+        out = DebugStats()
+        st = _load().ewald_debug_stats_read(self.handle, int(n), ctypes.byref(out))
+        if st != OK:
+            raise EwaldError(st, "ewald_debug_stats_read")
+        return {k: int(getattr(out, k)) for k, _ in DebugStats._fields_ if k != "reserved"}
 
     def profile(self, enable: bool = True):
         _load().ewald_profile_enable(self.handle, int(bool(enable)))

@@ -33,6 +33,7 @@ __all__ = [
     "perfect_rock_salt",
     "electrolyte",
     "random_neutral",
+    "clustered",
     "serving_mix",
     "CONFIGS",
     "make_config",
@@ -194,6 +195,37 @@ def random_neutral(n: int, box_L: float, seed: int, charge_scale: float = 1.0,
     if neutral and n > 1:
         q = q - q.mean()
     return pos, q
+
+
+def clustered(n_cluster: int, n_rest: int, box_L: float, corner, side: float, seed: int,
+              jitter: float = 0.3) -> Tuple[np.ndarray, np.ndarray]:
+    """A dense cluster inside a dilute background (edge case: crowded cells).
+
+    ``n_cluster`` ions sit on a jittered simple cubic grid filling the cube
+    [corner, corner + side)^3 (grid spacing s = side / ceil(n_cluster^(1/3)),
+    each site moved by U(-jitter s / 2, jitter s / 2)^3, so no two ions are
+    closer than (1 - jitter) s); charges alternate +-1 by the parity of the
+    grid site.  ``n_rest`` ions are uniform in the box outside that cube
+    (expanded by one grid spacing), with charges +-1 alternating in draw order.
+    Everything is drawn from ``default_rng(seed)``."""
+    rng = np.random.default_rng(seed)
+    m = int(math.ceil(n_cluster ** (1.0 / 3.0) - 1e-9))
+    sp = side / m
+    idx = np.arange(m ** 3)[:n_cluster]
+    i, j, k = idx // (m * m), (idx // m) % m, idx % m
+    base = np.asarray(corner, dtype=np.float64) + (np.stack([i, j, k], axis=1) + 0.5) * sp
+    pos_c = base + rng.uniform(-0.5 * jitter * sp, 0.5 * jitter * sp, size=base.shape)
+    q_c = np.where((i + j + k) % 2 == 0, 1.0, -1.0)
+    lo = np.asarray(corner, dtype=np.float64) - sp
+    hi = lo + side + 2 * sp
+    rest = np.empty((0, 3))
+    while rest.shape[0] < n_rest:
+        cand = rng.uniform(0.0, box_L, size=(2 * n_rest + 16, 3))
+        inside = np.all((cand >= lo) & (cand < hi), axis=1)
+        rest = np.concatenate([rest, cand[~inside]])
+    rest = rest[:n_rest]
+    q_r = np.where(np.arange(n_rest) % 2 == 0, 1.0, -1.0)
+    return np.concatenate([pos_c, rest]), np.concatenate([q_c, q_r])
 
 
 def _serving_system(args):

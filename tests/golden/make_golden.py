@@ -1,12 +1,19 @@
 """Write oracle reference values for the full-size workloads.
 
-Calls only the FP64 oracle (``oracle/``) and the seeded input generators.
-For each workload it stores: a checksum of the generated input, every energy
-part, S(k) at sampled half-space k vectors, and forces / dE/dq on sampled
-particles.  Usage:  python tests/golden/make_golden.py rocksalt64 electrolyte1m
+Every stored number is computed by the FP64 oracle (``oracle/``) from the
+seeded input generators; this script only chooses what to sample and writes
+JSON.  For each workload it stores: a checksum of the generated input, every
+energy part, S(k) at sampled half-space k vectors, and forces / dE/dq on
+sampled particles.
+
+The particle sample is stratified over space: the box is cut into
+``N_STRATA``^3 equal blocks and one particle is drawn from every non-empty
+block, so that every region of the box (every cell, every work item of the
+GPU path, whatever its placement) is represented.
+
+Usage:  python tests/golden/make_golden.py rocksalt64 electrolyte1m
 """
 import json
-import math
 import os
 import sys
 import time
@@ -21,7 +28,7 @@ import oracle  # noqa: E402
 from paper_1708_01135_amd import workloads as wl  # noqa: E402
 
 N_K_SAMPLES = 4096
-N_P_SAMPLES = 256
+N_STRATA = 16  # 16^3 = 4096 spatial blocks, one sampled particle each
 
 
 def input_checksum(s):
@@ -29,30 +36,36 @@ def input_checksum(s):
             "sum_q": float(np.sum(s.q)), "sum_qx": float(np.sum(s.q * s.pos[:, 0]))}
 
 
+def stratified_targets(pos, L, rng, strata=N_STRATA):
+    """One particle index drawn uniformly from each non-empty block of a
+    strata^3 grid over the (wrapped) box, in block order."""
+    w = np.mod(pos, L)
+    b = np.minimum((w / (L / strata)).astype(np.int64), strata - 1)
+    key = (b[:, 0] * strata + b[:, 1]) * strata + b[:, 2]
+    order = np.argsort(key, kind="stable")
+    skey = key[order]
+    starts = np.flatnonzero(np.r_[True, skey[1:] != skey[:-1]])
+    ends = np.r_[starts[1:], len(skey)]
+    pick = starts + (rng.random(len(starts)) * (ends - starts)).astype(np.int64)
+    return np.sort(order[pick])
+
+
 def make(name, seed=0):
     t0 = time.time()
     s = wl.make_config(name, seed)
     print(f"{name}: N={s.n} generated in {time.time() - t0:.1f}s", flush=True)
     rng = np.random.default_rng(12345 + seed)
-    targets = np.sort(rng.choice(s.n, N_P_SAMPLES, replace=False))
+    targets = stratified_targets(s.pos, s.box_L, rng)
     kv = oracle.kset(s.k_max, half=True)
     kidx = np.sort(rng.choice(len(kv), min(N_K_SAMPLES, len(kv)), replace=False))
     t0 = time.time()
-    e_real, f_real, p_real = oracle.real_space(s.pos, s.q, s.box_L, s.alpha, s.r_c, oracle.FAST)
-    print(f"  real space {time.time() - t0:.1f}s", flush=True)
-    t0 = time.time()
-    e_rec, f_rec, p_rec, sk = oracle.recip_space(s.pos, s.q, s.box_L, s.alpha, s.k_max, oracle.FAST,
-                                                 targets=targets, want_sk=True)
-    print(f"  reciprocal {time.time() - t0:.1f}s", flush=True)
-    q2, Q, V = float(np.sum(s.q * s.q)), float(np.sum(s.q)), s.box_L ** 3
-    e_self = -math.sqrt(s.alpha / math.pi) * q2
-    e_bg = -math.pi * Q * Q / (2 * V * s.alpha)
-    forces = f_real[targets] + f_rec
-    dEdq = p_real[targets] + p_rec - 2 * math.sqrt(s.alpha / math.pi) * s.q[targets] - math.pi * Q / (V * s.alpha)
+    energy, forces, dEdq, sk = oracle.energy_forces_targets(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max,
+                                                            targets=targets, method=oracle.FAST, want_sk=True)
+    print(f"  oracle {time.time() - t0:.1f}s, {len(targets)} targets", flush=True)
     out = {
         "workload": name, "seed": seed, "n": s.n, "box_L": s.box_L, "alpha": s.alpha, "r_c": s.r_c,
         "k_max": s.k_max, "input_checksum": input_checksum(s),
-        "energy": [e_real + e_rec + e_self + e_bg, e_real, e_rec, e_self, e_bg],
+        "energy": energy.tolist(),
         "targets": targets.tolist(), "forces": forces.tolist(), "dEdq": dEdq.tolist(),
         "k_samples": kv[kidx].tolist(), "sk_re": sk.real[kidx].tolist(), "sk_im": sk.imag[kidx].tolist(),
         "oracle_threads": oracle.num_threads(),

@@ -1,0 +1,81 @@
+"""GPU parity on the branches that ordinary inputs never reach.
+
+Every case here is legal under the C ABI (k_max <= 100, r_c <= L, any
+positions), and each asserts, through the plan's debug counters, that the
+branch it is meant for really ran:
+
+* k_max = 64, 84, 100: the vector-ALU structure factor (k_max > 47), fewer
+  rows per phase-table block (tables longer than 64 entries), and in FP64
+  the vector-ALU force gather (k_max > 83);
+* r_c = L: the largest cutoff the ABI takes (many images per pair);
+* a dense cluster in a dilute box: one cell with more than 2048 particles
+  (the cell sort's global-memory path) and particles with more neighbours
+  than the neighbour-list capacity (the direct loop).
+
+Bars are those of the other parity tests: relative norms and per-element
+maxima against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_01135_amd import workloads as wl
+
+from gpu_helpers import compare
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = ["fp64", "mixed"]
+
+
+def run_with_stats(pos, q, L, a, rc, K, precision):
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    dev = torch.device("cuda:0")
+    tp = torch.tensor(pos, dtype=torch.float64, device=dev)
+    tq = torch.tensor(q, dtype=torch.float64, device=dev)
+    with ew.Plan(len(q), L, a, rc, K, precision) as p:
+        e, f, g = p.energy_forces(tp, tq, True, True)
+        torch.cuda.synchronize()
+        st = p.status()
+        stats = p.debug_stats(len(q))
+        out = (e.cpu().numpy(), f.cpu().numpy(), g.cpu().numpy(), st)
+    print(f"stats {precision} K={K}: {stats}", flush=True)
+    return out, stats
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("K", [64, 84, 100])
+def test_large_k_max(K, precision):
+    n, L, a, rc = 150, 10.0, 1.0, 3.0
+    pos, q = wl.random_neutral(n, L, seed=K)
+    got, stats = run_with_stats(pos, q, L, a, rc, K, precision)
+    compare(got, oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST), precision, f"k_max={K}")
+    assert stats["sk_matrix_cores"] == 0            # k_max > 47: vector-ALU structure factor
+    assert stats["phase_rows"] < 64                  # tables longer than 64 entries
+    if precision == "fp64" and K > 83:
+        assert stats["gather_matrix_cores"] == 0     # z powers above 64 KB of LDS
+    elif precision == "mixed":
+        assert stats["gather_matrix_cores"] == 1
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_cutoff_equal_to_box(precision):
+    n, L, a, K = 240, 6.0, 1.2, 8
+    pos, q = wl.random_neutral(n, L, seed=77)
+    got, stats = run_with_stats(pos, q, L, a, L, K, precision)
+    compare(got, oracle.energy_forces(pos, q, L, a, L, K, oracle.FAST), precision, "r_c=L")
+    assert stats["cells_per_axis"] == 2
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_dense_cluster_fallbacks(precision):
+    # 3000 ions in a 1.6^3 cube inside one cell (h = 1.75), 3000 more spread
+    # over the 14^3 box: the cluster's cell holds > 2048 particles and its ions
+    # have about 50x the neighbours the plan's mean density predicts.
+    L, a, rc, K = 14.0, 1.0, 3.5, 10
+    pos, q = wl.clustered(3000, 3000, L, (0.05, 0.05, 0.05), 1.6, seed=11)
+    got, stats = run_with_stats(pos, q, L, a, rc, K, precision)
+    compare(got, oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST), precision, "cluster")
+    assert stats["max_cell_count"] > 2048
+    assert stats["direct_particles"] >= 3000

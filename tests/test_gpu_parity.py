@@ -24,7 +24,7 @@ def ref(pos, q, L, a, rc, K):
 
 SMALL_CASES = [
     # name, n, L, alpha, r_c, K
-    ("single_cell_rc_gt_halfL", 37, 5.0, 1.1, 4.6, 6),   # nc = 1, many images
+    ("single_cell_rc_gt_halfL", 37, 5.0, 1.1, 4.6, 6),   # nc = 2 (h >= r_c / 2), many images
     ("two_cells", 200, 6.0, 1.3, 2.9, 7),                 # nc = 2
     ("odd_ragged", 1001, 10.0, 0.9, 3.2, 9),               # nc = 3, ragged tail
     ("k_row_boundaries", 777, 9.0, 1.0, 3.0, 16),          # K a multiple of the segment width
@@ -122,7 +122,8 @@ def test_structure_factor_matches_oracle(precision):
     idx = np.array([lookup[tuple(v)] for v in kv])
     assert len(set(idx.tolist())) == len(kref)
     err = np.abs(sk - sk_ref[idx]).max()
-    assert err < (1e-11 if precision == "fp64" else 2e-5 * math.sqrt(len(s.q))), err
+    # the structure factor is FP64 (phases and sums) in both precisions
+    assert err < 1e-11, err
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
@@ -137,7 +138,7 @@ def test_closed_form_lattice_structure_factor(precision):
         sk = p.structure_factor()
     special = np.all(np.mod(kv, 8) == 4, axis=1)
     expect = np.where(special, 512.0, 0.0)
-    assert np.abs(sk - expect).max() < (1e-10 if precision == "fp64" else 1e-3)
+    assert np.abs(sk - expect).max() < 1e-10  # FP64 structure factor in both precisions
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)

@@ -229,6 +229,28 @@ def test_real_space_targets_match_full():
     assert np.abs(pt - ph[t]).max() < 1e-13
 
 
+@pytest.mark.parametrize("method", [oracle.BRUTE, oracle.FAST])
+def test_target_assembly_matches_full_evaluation(method):
+    """The entry point that writes the stored full-size references assembles
+    forces and dE/dq of the listed particles; it must reproduce the full
+    evaluation (pinned above) at those particles, and its S_k the direct sums."""
+    pos, q = wl.random_neutral(300, 7.0, seed=5, neutral=False)
+    e, f, d = oracle.energy_forces(pos, q, 7.0, 1.0, 3.4, 9, method)
+    t = [3, 17, 299, 0, 150, 17]
+    if method == oracle.FAST:
+        e2, f2, d2, sk = oracle.energy_forces_targets(pos, q, 7.0, 1.0, 3.4, 9, targets=t, method=method,
+                                                      want_sk=True)
+        sk_direct = oracle.structure_factor(pos, q, 7.0, oracle.kset(9, half=True))
+        assert np.abs(sk - sk_direct).max() < 1e-11
+    else:
+        e2, f2, d2 = oracle.energy_forces_targets(pos, q, 7.0, 1.0, 3.4, 9, targets=t, method=method)
+    assert np.array_equal(e, e2)
+    assert np.abs(f2 - f[t]).max() <= 1e-14 * np.abs(f).max()
+    assert np.abs(d2 - d[t]).max() <= 1e-14 * np.abs(d).max()
+    e3, f3, d3 = oracle.energy_forces_targets(pos, q, 7.0, 1.0, 3.4, 9, method=method)
+    assert np.array_equal(f3, f) and np.array_equal(d3, d)
+
+
 # ----------------------------------------------------- spherical image sums
 
 def _shell_energy(pos, q, L, R):
