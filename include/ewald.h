@@ -74,7 +74,9 @@ typedef enum {
     EWALD_ERR_OUT_OF_MEMORY = -3, /* device or host allocation failed             */
     EWALD_ERR_DEVICE = -4,        /* a HIP runtime call or kernel launch failed   */
     EWALD_ERR_NONFINITE = -5,     /* a position or charge was NaN or infinite     */
-    EWALD_ERR_ADMISSION = -6      /* workspace above a server's free HBM budget   */
+    EWALD_ERR_ADMISSION = -6,     /* workspace above a server's free HBM budget   */
+    EWALD_ERR_SCRATCH = -7        /* buffers of an allocation-free evaluation
+                                     exceed EWALD_SCRATCH_BYTES                   */
 } ewald_status;
 
 /* Arithmetic of the hot kernels. */
@@ -105,7 +107,12 @@ enum {
  *              instead of the matrix cores (same results to rounding; used to
  *              compare the two), and
  *                EWALD_FLAG_NO_GRAPH     always launch kernel by kernel (see
- *                                        "Graph replay" below).
+ *                                        "Graph replay" below),
+ *                EWALD_FLAG_NO_WORKSPACE allocate only the plan's constant tables
+ *                                        (a few MB at most); such a plan is
+ *                                        evaluated with ewald_energy_forces_noalloc()
+ *                                        alone (every other evaluation and debug
+ *                                        call returns EWALD_ERR_INVALID_ARG).
  *              Other bits are invalid.  The vector kernels are
  *              also used where the matrix-core ones do not fit: the gather when a
  *              block's staged z powers would exceed 64 KB of LDS (FP64 with
@@ -126,6 +133,10 @@ typedef struct {
 #define EWALD_FLAG_VALU_GATHER 1
 #define EWALD_FLAG_VALU_SK 2
 #define EWALD_FLAG_NO_GRAPH 4
+#define EWALD_FLAG_NO_WORKSPACE 8
+
+/* Size of the per-device static scratch of ewald_energy_forces_noalloc(). */
+#define EWALD_SCRATCH_BYTES ((size_t)64 << 20)
 
 /* Static description of a status code (never NULL). */
 const char *ewald_status_string(ewald_status status);
@@ -179,6 +190,27 @@ ewald_status ewald_energy(ewald_plan_t plan, int64_t n, const double *pos, const
  * ewald_energy_forces, plus INVALID_ARG for a NULL grad_energy. */
 ewald_status ewald_energy_backward(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
                                    const double *grad_energy, double *energy, double *grad_pos, double *grad_q);
+
+/* Allocation-free variant of ewald_energy_forces(), for callers that cannot
+ * allocate device memory while they evaluate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * results (bitwise: the same kernels with the same launch shapes) and errors,
+ * except that the per-evaluation buffers (cell list, neighbour lists, phase
+ * tables, structure-factor partials, gather partials) are carved from a
+ * static device array of EWALD_SCRATCH_BYTES that the library holds on every
+ * device it runs on, until the process ends, instead of from the plan's
+ * workspace.  The plan may have been made with EWALD_FLAG_NO_WORKSPACE.
+ *   - Nothing is allocated: no hipMalloc, hipFree, event or graph creation; the
+ *     kernels are launched one by one (no graph replay, no profiling).  The
+ *     counters that must start at zero are cleared by a fill kernel.
+ *   - Returns EWALD_ERR_SCRATCH, with nothing enqueued, when the buffers for n
+ *     particles at the plan's k_max and cell grid exceed EWALD_SCRATCH_BYTES
+ *     (about 12,000 ions at the density and cutoffs of the 32^3 rock salt).
+ *   - All calls on one device share that device's array, which keeps the last
+ *     call's contents: calls that may overlap on one device (any plans, any
+ *     streams) race and give wrong results; the caller serialises them. */
+ewald_status ewald_energy_forces_noalloc(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
+                                         double *energy, double *forces, double *dEdq);
 
 /* Synchronise the plan's stream, then return and clear the status latched by
  * device-side checks (EWALD_OK if none). */

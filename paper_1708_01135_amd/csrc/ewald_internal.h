@@ -75,6 +75,8 @@ struct CellArgs {
     int nc;
     int ncell;
 };
+// Zero `bytes` (a multiple of 16, 16-byte aligned) at p with a fill kernel.
+hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
 hipError_t launch_bin(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_of,
                       int *counts, double *qpart, int *status);
 hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill, int *cell_start,

@@ -11,6 +11,8 @@
 //   scan     : exclusive scan of the counts (one workgroup), total charge;
 //   scatter  : slot claim inside each cell (order not yet deterministic);
 //   cellsort : per cell, rank by input index and write the sorted records.
+#include <algorithm>
+
 #include "ewald_internal.h"
 
 namespace ewk {
@@ -196,7 +198,24 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
     }
 }
 
+// Clears `words` 16-byte words (the counters and padding an evaluation expects
+// at zero, when its buffers come from memory another evaluation used).
+__global__ __launch_bounds__(256) void k_zero(uint4 *__restrict__ p, int64_t words)
+{
+    const uint4 z = {0u, 0u, 0u, 0u};
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256) p[i] = z;
+}
+
 }  // namespace
+
+hipError_t launch_zero(hipStream_t s, void *p, size_t bytes)
+{
+    const int64_t words = (int64_t)(bytes / sizeof(uint4));
+    if (words == 0) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>(ceil_div(words, 256), 2048);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, static_cast<uint4 *>(p), words);
+    return hipGetLastError();
+}
 
 hipError_t launch_bin(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_of,
                       int *counts, double *qpart, int *status)

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -364,11 +365,18 @@ T *carve(char *&cur, size_t bytes)
     return r;
 }
 
+// The buffers that must hold zeros when an evaluation starts come first, so
+// that one fill clears them: the cell counters (each evaluation leaves them
+// cleared again) and the tile coefficients, whose padding entries are never
+// written.
+size_t zeroed_bytes(const Sizes &z) { return z.counts + z.fill + z.mcoef; }
+
 void carve_work(char *cur, const Sizes &z, Work &w)
 {
-    w.cell_of = carve<int>(cur, z.cell_of);
     w.counts = carve<int>(cur, z.counts);
     w.fill = carve<int>(cur, z.fill);
+    w.mcoef = carve<void>(cur, z.mcoef);
+    w.cell_of = carve<int>(cur, z.cell_of);
     w.cell_start = carve<int>(cur, z.cell_start);
     w.tmp_idx = carve<int>(cur, z.tmp_idx);
     w.perm = carve<int>(cur, z.perm);
@@ -390,7 +398,6 @@ void carve_work(char *cur, const Sizes &z, Work &w)
     w.n_pitems = carve<int>(cur, z.n_pitems);
     w.plist = carve<uint32_t>(cur, z.plist);
     w.plist_cnt = carve<int>(cur, z.plist_cnt);
-    w.mcoef = carve<void>(cur, z.mcoef);
     w.pr = carve<d4>(cur, z.pr);
     w.max_chunks = z.max_chunks;
     w.list_cap = z.list_cap;
@@ -400,6 +407,38 @@ struct ProfRec {
     int kind;
     hipEvent_t a, b;
 };
+
+}  // namespace
+
+// Per-evaluation buffers of ewald_energy_forces_noalloc(): one copy on every
+// device the library runs on, held until the process ends.  Host code never
+// passes this name to a kernel or a copy (on the host it is only a stand-in
+// for the symbol); it uses the device address resolved once per device by
+// scratch_address() below.
+static __device__ __align__(256) unsigned char scratch[EWALD_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of this device's copy of `scratch`, resolved on the first
+// call per device (with that device current) and kept; nullptr on failure.
+void *scratch_address(int dev)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -420,6 +459,7 @@ struct ewald_plan_s {
     Sizes sz{};
     void *base = nullptr;
     bool has_work = true;  // false: EWALD_FLAG_NO_WORKSPACE (tables only)
+    void *scratch = nullptr;  // this device's static scratch (allocation-free evaluation)
     // plan-resident tables and status word
     int *status = nullptr;
     double *ck = nullptr;
@@ -543,6 +583,7 @@ const char *ewald_status_string(ewald_status s)
     case EWALD_ERR_DEVICE: return "HIP device or launch error";
     case EWALD_ERR_NONFINITE: return "non-finite position or charge";
     case EWALD_ERR_ADMISSION: return "plan workspace exceeds the server's free HBM budget";
+    case EWALD_ERR_SCRATCH: return "buffers for this n exceed the static scratch (EWALD_SCRATCH_BYTES)";
     }
     return "unknown status";
 }
@@ -556,7 +597,8 @@ ewald_status ewald_params_validate(const ewald_params *p)
     if (!(std::isfinite(p->r_c) && p->r_c > 0.0 && p->r_c <= p->box_L)) return EWALD_ERR_INVALID_ARG;
     if (p->k_max < 1 || p->k_max > EWALD_K_MAX_LIMIT) return EWALD_ERR_INVALID_ARG;
     if (p->precision != EWALD_PRECISION_FP64 && p->precision != EWALD_PRECISION_MIXED) return EWALD_ERR_INVALID_ARG;
-    if (p->device < 0 || (p->flags & ~(EWALD_FLAG_VALU_GATHER | EWALD_FLAG_VALU_SK | EWALD_FLAG_NO_GRAPH)) != 0)
+    if (p->device < 0 || (p->flags & ~(EWALD_FLAG_VALU_GATHER | EWALD_FLAG_VALU_SK | EWALD_FLAG_NO_GRAPH |
+                                       EWALD_FLAG_NO_WORKSPACE)) != 0)
         return EWALD_ERR_INVALID_ARG;
     return EWALD_OK;
 }
@@ -601,7 +643,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->ncell = p->nc * p->nc * p->nc;
     build_klayout(params->k_max, p->kl, !p->mixed);
     p->tile = sk_tile(params->k_max + 1);
-    p->has_work = true;
+    p->has_work = !(params->flags & EWALD_FLAG_NO_WORKSPACE);
     compute_sizes(*params, p->kl, p->nc, params->n_max, p->sz);
 
     int ndev = 0;
@@ -611,6 +653,12 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     }
     DeviceGuard dg(p->device);
     if (!dg.ok()) {
+        delete p;
+        return EWALD_ERR_DEVICE;
+    }
+    // set-up of the allocation-free evaluation on this device
+    p->scratch = scratch_address(p->device);
+    if (!p->has_work && !p->scratch) {
         delete p;
         return EWALD_ERR_DEVICE;
     }
@@ -725,7 +773,7 @@ namespace {
 // given, turns the force / dE/dq outputs into the adjoint.
 ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_stream, int64_t n,
                          const double *pos, const double *q, double *energy, double *forces, double *dEdq,
-                         const double *gscale, bool energy_only)
+                         const double *gscale, bool energy_only, bool allow_prof = true)
 {
     const KLayout &kl = p->kl;
     const double L = p->prm.box_L;
@@ -755,7 +803,7 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
 
     hipError_t e = hipSuccess;
     auto run = [&](hipStream_t st, int kind, auto &&fn) {
-        if (e == hipSuccess) e = timed(p, st, kind, fn);
+        if (e == hipSuccess) e = allow_prof ? timed(p, st, kind, fn) : fn();
     };
     // Reciprocal space on the plan's own stream, from the caller's positions and
     // charges: it needs nothing from the cell list, so it runs beside the real
@@ -852,6 +900,7 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
 ewald_status run_path(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy, double *forces,
                       double *dEdq, const double *gscale, bool energy_only)
 {
+    if (!p->has_work) return EWALD_ERR_INVALID_ARG;
     if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
     DeviceGuard dg(p->device);
     if (!dg.ok()) return EWALD_ERR_DEVICE;
@@ -949,6 +998,28 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
     return run_path(p, n, pos, q, energy, forces, dEdq, nullptr, false);
 }
 
+ewald_status ewald_energy_forces_noalloc(ewald_plan_t p, int64_t n, const double *pos, const double *q,
+                                         double *energy, double *forces, double *dEdq)
+{
+    if (!p || !pos || !q || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    Sizes z;
+    compute_sizes(p->prm, p->kl, p->nc, n, z);
+    if (z.work > EWALD_SCRATCH_BYTES) return EWALD_ERR_SCRATCH;
+    if (!p->scratch) return EWALD_ERR_DEVICE;
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    Work w;
+    carve_work(static_cast<char *>(p->scratch), z, w);
+    // the array keeps whatever the last call on this device left in it
+    if (launch_zero(p->stream, p->scratch, zeroed_bytes(z)) != hipSuccess) {
+        (void)hipGetLastError();
+        return EWALD_ERR_DEVICE;
+    }
+    p->last_graph = false;  // this call's join event marks its completion
+    return launch_path(p, w, p->stream, false, n, pos, q, energy, forces, dEdq, nullptr, false, false);
+}
+
 ewald_status ewald_energy(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy)
 {
     if (!p || !pos || !q || !energy || n < 1) return EWALD_ERR_INVALID_ARG;
@@ -1044,7 +1115,7 @@ ewald_status ewald_debug_kset(ewald_plan_t p, int32_t *n_xyz)
 
 ewald_status ewald_debug_copy_sk(ewald_plan_t p, double *re, double *im)
 {
-    if (!p || !re || !im) return EWALD_ERR_INVALID_ARG;
+    if (!p || !re || !im || !p->has_work) return EWALD_ERR_INVALID_ARG;
     DeviceGuard dg(p->device);
     if (!dg.ok()) return EWALD_ERR_DEVICE;
     const int n_slots = p->kl.n_units * kQ * kLanes;
@@ -1065,7 +1136,7 @@ ewald_status ewald_debug_copy_sk(ewald_plan_t p, double *re, double *im)
 
 ewald_status ewald_debug_stats_read(ewald_plan_t p, int64_t n, ewald_debug_stats *out)
 {
-    if (!p || !out || n < 1 || n > p->prm.n_max) return EWALD_ERR_INVALID_ARG;
+    if (!p || !out || n < 1 || n > p->prm.n_max || !p->has_work) return EWALD_ERR_INVALID_ARG;
     DeviceGuard dg(p->device);
     if (!dg.ok()) return EWALD_ERR_DEVICE;
     std::vector<int> cs((size_t)p->ncell + 1), cnt((size_t)n);

@@ -21,6 +21,7 @@ ERR_OUT_OF_MEMORY = -3
 ERR_DEVICE = -4
 ERR_NONFINITE = -5
 ERR_ADMISSION = -6
+ERR_SCRATCH = -7
 
 FP64 = 0
 MIXED = 1
@@ -28,6 +29,8 @@ K_MAX_LIMIT = 100
 FLAG_VALU_GATHER = 1
 FLAG_VALU_SK = 2
 FLAG_NO_GRAPH = 4
+FLAG_NO_WORKSPACE = 8
+SCRATCH_BYTES = 64 << 20  # EWALD_SCRATCH_BYTES
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
 
@@ -95,6 +98,8 @@ def _load():
     lib.ewald_plan_set_stream.argtypes = [vp, vp]
     lib.ewald_energy_forces.restype = ctypes.c_int
     lib.ewald_energy_forces.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    lib.ewald_energy_forces_noalloc.restype = ctypes.c_int
+    lib.ewald_energy_forces_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.ewald_energy.restype = ctypes.c_int
     lib.ewald_energy.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     lib.ewald_energy_backward.restype = ctypes.c_int
@@ -232,6 +237,25 @@ class Plan:
                                      g.data_ptr() if g is not None else None)
         if st != OK:
             raise EwaldError(st, "ewald_energy_forces")
+        return e, f, g
+
+    def energy_forces_noalloc(self, pos, q, out):
+        """The allocation-free evaluation: ``out`` = (energy[5], forces (n,3) or
+        None, dEdq (n,) or None), preallocated float64 device tensors, is
+        overwritten; the library's static scratch holds every other buffer."""
+        import torch
+        n = self._check_inputs(pos, q)
+        e, f, g = out
+        for name, t, shape in (("energy", e, (5,)), ("forces", f, (n, 3)), ("dEdq", g, (n,))):
+            if t is None and name != "energy":
+                continue
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        st = _load().ewald_energy_forces_noalloc(self.handle, n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
+                                                 f.data_ptr() if f is not None else None,
+                                                 g.data_ptr() if g is not None else None)
+        if st != OK:
+            raise EwaldError(st, "ewald_energy_forces_noalloc")
         return e, f, g
 
     def _check_inputs(self, pos, q):

@@ -31,15 +31,16 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for st in (0, -1, -2, -3, -4, -5, -6):
+    for st in (0, -1, -2, -3, -4, -5, -6, -7):
         assert ew.status_string(st)
     assert "unknown" in ew.status_string(7)
+    assert "scratch" in ew.status_string(ew.ERR_SCRATCH)
 
 
 BAD = [
     dict(n_max=0), dict(n_max=(1 << 25) + 1), dict(box_L=0.0), dict(box_L=-1.0), dict(box_L=float("nan")), dict(alpha=0.0),
     dict(alpha=float("inf")), dict(r_c=0.0), dict(r_c=8.5), dict(k_max=0), dict(k_max=ew.K_MAX_LIMIT + 1),
-    dict(precision=2), dict(device=-1), dict(flags=8), dict(flags=-1),
+    dict(precision=2), dict(device=-1), dict(flags=16), dict(flags=-1),
 ]
 
 
