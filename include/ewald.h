@@ -108,6 +108,11 @@ enum {
  *              compare the two), and
  *                EWALD_FLAG_NO_GRAPH     always launch kernel by kernel (see
  *                                        "Graph replay" below),
+ *                EWALD_FLAG_ONE_STREAM   run the reciprocal-space chain on the plan's
+ *                                        stream too, before the real-space one,
+ *                                        instead of beside it on a second stream
+ *                                        (same results; per-kernel timings then
+ *                                        measure each kernel alone),
  *                EWALD_FLAG_NO_WORKSPACE allocate only the plan's constant tables
  *                                        (a few MB at most); such a plan is
  *                                        evaluated with ewald_energy_forces_noalloc()
@@ -134,6 +139,7 @@ typedef struct {
 #define EWALD_FLAG_VALU_SK 2
 #define EWALD_FLAG_NO_GRAPH 4
 #define EWALD_FLAG_NO_WORKSPACE 8
+#define EWALD_FLAG_ONE_STREAM 16
 
 /* Size of the per-device static scratch of ewald_energy_forces_noalloc(). */
 #define EWALD_SCRATCH_BYTES ((size_t)64 << 20)

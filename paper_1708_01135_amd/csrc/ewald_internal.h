@@ -79,9 +79,12 @@ struct CellArgs {
 hipError_t launch_zero(hipStream_t s, void *p, size_t bytes);
 hipError_t launch_bin(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_of,
                       int *counts, double *qpart, int *status);
+// Two launches: tile totals (and the charge sums), then the per-tile scans.
+// tile_sums holds scan_tiles(ncell) entries.
+int scan_tiles(int ncell);
 hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill, int *cell_start,
-                       const double *qpart, int n_qblocks, double *scalars, int *item_cell, int *item_off,
-                       int *n_items);
+                       const double *qpart, int n_qblocks, double *scalars, int2 *tile_sums, int *item_cell,
+                       int *item_off, int *n_items);
 hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, const int *cell_start,
                           int *fill, int *tmp_idx);
 hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, const int *tmp_idx,

@@ -8,7 +8,8 @@
 // (section 2.2); here it is four short kernels:
 //   bin      : wrap, cell id, per-cell counts (integer atomics), charge sums,
 //              non-finite detection;
-//   scan     : exclusive scan of the counts (one workgroup), total charge;
+//   scan     : exclusive scan of the counts (tile totals, then one block per
+//              tile), pair-loop work items, total charge;
 //   scatter  : slot claim inside each cell (order not yet deterministic);
 //   cellsort : per cell, rank by input index and write the sorted records.
 #include <algorithm>
@@ -67,64 +68,65 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc
     }
 }
 
-constexpr int kScanThreads = 1024;
+constexpr int kScanThreads = 256;
+constexpr int kScanPer = 4;                           // cells per thread
+constexpr int kScanTile = kScanThreads * kScanPer;    // cells per block
 
-// One workgroup: exclusive scan of the cell counts into cell_start (ncell+1
-// entries), then counts and fill are cleared for the next evaluation.  Also
-// reduces the per-block charge sums into scalars[0] = Q, scalars[1] = sum q^2.
-__global__ __launch_bounds__(kScanThreads) void k_scan(int ncell, int *__restrict__ counts,
-                                                       int *__restrict__ fill, int *__restrict__ cell_start,
-                                                       const double *__restrict__ qpart, int n_qblocks,
-                                                       double *__restrict__ scalars, int *__restrict__ item_cell,
-                                                       int *__restrict__ item_off, int *__restrict__ n_items)
+// Counts of the kScanPer consecutive cells c0 .. c0 + kScanPer - 1 (zero past
+// ncell): one 16-byte load when the whole group lies inside the array.
+__device__ inline int4 load_counts(const int *__restrict__ counts, int c0, int ncell)
 {
-    __shared__ int s_sum[kScanThreads];
-    __shared__ int s_items[kScanThreads];
+    if (c0 + kScanPer <= ncell) return *reinterpret_cast<const int4 *>(counts + c0);
+    int4 v = {0, 0, 0, 0};
+    if (c0 < ncell) v.x = counts[c0];
+    if (c0 + 1 < ncell) v.y = counts[c0 + 1];
+    if (c0 + 2 < ncell) v.z = counts[c0 + 2];
+    return v;
+}
+
+__device__ inline int items_of(int k) { return (k + kPairHome - 1) / kPairHome; }
+
+// Block-wide sums (sum over all threads) of two integers.
+__device__ inline int2 block_sum2(int a, int b, int2 *s_w)
+{
+    const int lane = (int)threadIdx.x % kLanes, wave = (int)threadIdx.x / kLanes;
+#pragma unroll
+    for (int d = kLanes / 2; d > 0; d >>= 1) {
+        a += __shfl_xor(a, d);
+        b += __shfl_xor(b, d);
+    }
+    if (lane == 0) s_w[wave] = make_int2(a, b);
+    __syncthreads();
+    int2 t = {0, 0};
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kLanes; ++w) {
+        t.x += s_w[w].x;
+        t.y += s_w[w].y;
+    }
+    __syncthreads();  // s_w may be reused
+    return t;
+}
+
+// Pass 1 of the cell scan, one block per tile of kScanTile cells: the tile's
+// particle and pair-work-item totals.  Block n_tiles (the last one) instead
+// reduces the per-block charge sums of the binning into scalars[0] = Q and
+// scalars[1] = sum q^2, in a fixed order (contiguous ranges, then a fixed tree).
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ncell, int n_tiles, const int *__restrict__ counts,
+                                                             int2 *__restrict__ tile_sums,
+                                                             const double *__restrict__ qpart, int n_qblocks,
+                                                             double *__restrict__ scalars)
+{
+    __shared__ int2 s_w[kScanThreads / kLanes];
     __shared__ double s_a[kScanThreads];
     __shared__ double s_b[kScanThreads];
-    const int t = threadIdx.x;
-    const int per = (ncell + kScanThreads - 1) / kScanThreads;
-    const int lo = t * per < ncell ? t * per : ncell;
-    const int hi = lo + per < ncell ? lo + per : ncell;
-    // pair-loop work items: one per (cell, kPairHome home particles)
-    int local = 0, litems = 0;
-    for (int c = lo; c < hi; ++c) {
-        const int k = counts[c];
-        local += k;
-        litems += (k + kPairHome - 1) / kPairHome;
+    const int t = (int)threadIdx.x;
+    if ((int)blockIdx.x < n_tiles) {
+        const int4 v = load_counts(counts, (int)blockIdx.x * kScanTile + t * kScanPer, ncell);
+        const int2 tot = block_sum2(v.x + v.y + v.z + v.w, items_of(v.x) + items_of(v.y) + items_of(v.z) + items_of(v.w),
+                                    s_w);
+        if (t == 0) tile_sums[blockIdx.x] = tot;
+        return;
     }
-    s_sum[t] = local;
-    s_items[t] = litems;
-    __syncthreads();
-    // Hillis-Steele inclusive scans over the per-thread sums
-    for (int off = 1; off < kScanThreads; off <<= 1) {
-        const int v = t >= off ? s_sum[t - off] : 0;
-        const int w = t >= off ? s_items[t - off] : 0;
-        __syncthreads();
-        s_sum[t] += v;
-        s_items[t] += w;
-        __syncthreads();
-    }
-    int run = s_sum[t] - local;
-    int irun = s_items[t] - litems;
-    for (int c = lo; c < hi; ++c) {
-        const int k = counts[c];
-        cell_start[c] = run;
-        run += k;
-        for (int o = 0; o < k; o += kPairHome) {
-            item_cell[irun] = c;
-            item_off[irun] = o;
-            ++irun;
-        }
-        counts[c] = 0;
-        fill[c] = 0;
-    }
-    if (t == kScanThreads - 1) {
-        cell_start[ncell] = s_sum[t];
-        *n_items = s_items[t];
-    }
-
-    // charge sums in a fixed order: contiguous ranges, then a fixed tree
     const int qper = (n_qblocks + kScanThreads - 1) / kScanThreads;
     double a = 0.0, b = 0.0;
     for (int k = t * qper; k < (t + 1) * qper && k < n_qblocks; ++k) {
@@ -144,6 +146,83 @@ __global__ __launch_bounds__(kScanThreads) void k_scan(int ncell, int *__restric
     if (t == 0) {
         scalars[0] = s_a[0];
         scalars[1] = s_b[0];
+    }
+}
+
+// Pass 2, one block per tile: the tile's offset is the sum of the earlier
+// tiles' totals; an exclusive scan of the counts inside the tile (wave
+// shuffles, then the waves' totals) gives cell_start, and the pair-loop work
+// items (one per cell and kPairHome home particles, in cell order) are written
+// at the matching item offsets as (cell, offset of the first home particle).  Counts and fill are cleared for the next
+// evaluation.  The last block writes cell_start[ncell] and the item count.
+__global__ __launch_bounds__(kScanThreads) void k_scan_cells(int ncell, int n_tiles, int *__restrict__ counts,
+                                                             int *__restrict__ fill,
+                                                             const int2 *__restrict__ tile_sums,
+                                                             int *__restrict__ cell_start, int *__restrict__ item_cell,
+                                                             int *__restrict__ item_off, int *__restrict__ n_items)
+{
+    __shared__ int2 s_w[kScanThreads / kLanes];
+    const int t = (int)threadIdx.x, lane = t % kLanes, wave = t / kLanes;
+    const int b = (int)blockIdx.x;
+    int pa = 0, pb = 0;
+    for (int k = t; k < b; k += kScanThreads) {
+        const int2 v = tile_sums[k];
+        pa += v.x;
+        pb += v.y;
+    }
+    const int2 base = block_sum2(pa, pb, s_w);
+    const int c0 = b * kScanTile + t * kScanPer;
+    const int4 v = load_counts(counts, c0, ncell);
+    const int cnt[kScanPer] = {v.x, v.y, v.z, v.w};
+    int la = 0, lb = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        la += cnt[u];
+        lb += items_of(cnt[u]);
+    }
+    // inclusive scans inside each wave
+    int ia = la, ib = lb;
+#pragma unroll
+    for (int d = 1; d < kLanes; d <<= 1) {
+        const int xa = __shfl_up(ia, d), xb = __shfl_up(ib, d);
+        if (lane >= d) {
+            ia += xa;
+            ib += xb;
+        }
+    }
+    if (lane == kLanes - 1) s_w[wave] = make_int2(ia, ib);
+    __syncthreads();
+    int wa = 0, wb = 0, ta = 0, tb = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kLanes; ++w) {
+        const int2 x = s_w[w];
+        if (w < wave) {
+            wa += x.x;
+            wb += x.y;
+        }
+        ta += x.x;
+        tb += x.y;
+    }
+    int run = base.x + wa + ia - la;
+    int irun = base.y + wb + ib - lb;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        const int c = c0 + u;
+        if (c < ncell) {
+            cell_start[c] = run;
+            run += cnt[u];
+            for (int o = 0; o < cnt[u]; o += kPairHome) {
+                item_cell[irun] = c;
+                item_off[irun] = o;
+                ++irun;
+            }
+            counts[c] = 0;
+            fill[c] = 0;
+        }
+    }
+    if (b == n_tiles - 1 && t == 0) {
+        cell_start[ncell] = base.x + ta;
+        *n_items = base.y + tb;
     }
 }
 
@@ -226,13 +305,20 @@ hipError_t launch_bin(hipStream_t s, const CellArgs &a, const double *pos, const
 }
 
 hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill, int *cell_start,
-                       const double *qpart, int n_qblocks, double *scalars, int *item_cell, int *item_off,
-                       int *n_items)
+                       const double *qpart, int n_qblocks, double *scalars, int2 *tile_sums, int *item_cell,
+                       int *item_off, int *n_items)
 {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(kScanThreads), 0, s, a.ncell, counts, fill, cell_start, qpart,
-                       n_qblocks, scalars, item_cell, item_off, n_items);
+    const int n_tiles = scan_tiles(a.ncell);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles + 1), dim3(kScanThreads), 0, s, a.ncell, n_tiles, counts,
+                       tile_sums, qpart, n_qblocks, scalars);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scan_cells, dim3(n_tiles), dim3(kScanThreads), 0, s, a.ncell, n_tiles, counts, fill,
+                       tile_sums, cell_start, item_cell, item_off, n_items);
     return hipGetLastError();
 }
+
+int scan_tiles(int ncell) { return ceil_div(ncell, kScanTile); }
 
 hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, const int *cell_start,
                           int *fill, int *tmp_idx)

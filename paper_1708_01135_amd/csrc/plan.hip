@@ -268,7 +268,7 @@ struct Sizes {
     size_t pq, freal, qpart, scalars, epart, erec, ck;
     size_t tx, part, sk, rec, gpart;
     size_t row_nx, row_ny, row_m, unit_g, unit_s, row_item, item_nx, item_ny, item_seg;
-    size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt;
+    size_t pitem_cell, pitem_off, n_pitems, plist, plist_cnt, tile_sums;
     size_t mcoef, mtiles, row_mbase, unit_base, sk_tile_of, pr;
     size_t tables, work, total;
     int max_chunks;
@@ -323,9 +323,10 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, int64_t N, 
     z.row_item = align_up(sizeof(int) * kl.row_item.size());
     z.item_nx = z.item_ny = z.item_seg = align_up(sizeof(int) * (size_t)std::max(kl.n_items, 1));
     z.max_pitems = (int)ncell + ceil_div(N, kPairHome);
-    z.list_cap = pair_list_cap(p);
     z.pitem_cell = z.pitem_off = align_up(sizeof(int) * (size_t)z.max_pitems);
     z.n_pitems = align_up(sizeof(int));
+    z.tile_sums = align_up(sizeof(int2) * (size_t)scan_tiles((int)ncell));
+    z.list_cap = pair_list_cap(p);
     z.plist = align_up(sizeof(uint32_t) * (size_t)z.list_cap * N);
     z.plist_cnt = align_up(sizeof(int) * N);
     z.mcoef = align_up(real * (size_t)kl.m_blocks * kMBlock);
@@ -338,7 +339,7 @@ void compute_sizes(const ewald_params &p, const KLayout &kl, int nc, int64_t N, 
                z.unit_base + z.sk_tile_of;
     z.work = z.cell_of + z.counts + z.fill + z.cell_start + z.tmp_idx + z.perm + z.pq + z.freal + z.qpart +
              z.scalars + z.epart + z.erec + 3 * z.tx + z.part + z.sk + z.rec + z.gpart + 2 * z.pitem_cell +
-             z.n_pitems + z.plist + z.plist_cnt + z.mcoef + z.pr;
+             z.n_pitems + z.plist + z.plist_cnt + z.mcoef + z.pr + z.tile_sums;
     z.total = z.tables + z.work;
 }
 
@@ -354,6 +355,7 @@ struct Work {
     uint32_t *plist = nullptr;
     void *mcoef = nullptr;
     d4 *pr = nullptr;  // caller-order particle records of the reciprocal kernels
+    int2 *tile_sums = nullptr;  // cell-scan tile totals
     int max_chunks = 1, list_cap = 1;
 };
 
@@ -399,6 +401,7 @@ void carve_work(char *cur, const Sizes &z, Work &w)
     w.plist = carve<uint32_t>(cur, z.plist);
     w.plist_cnt = carve<int>(cur, z.plist_cnt);
     w.pr = carve<d4>(cur, z.pr);
+    w.tile_sums = carve<int2>(cur, z.tile_sums);
     w.max_chunks = z.max_chunks;
     w.list_cap = z.list_cap;
 }
@@ -598,7 +601,7 @@ ewald_status ewald_params_validate(const ewald_params *p)
     if (p->k_max < 1 || p->k_max > EWALD_K_MAX_LIMIT) return EWALD_ERR_INVALID_ARG;
     if (p->precision != EWALD_PRECISION_FP64 && p->precision != EWALD_PRECISION_MIXED) return EWALD_ERR_INVALID_ARG;
     if (p->device < 0 || (p->flags & ~(EWALD_FLAG_VALU_GATHER | EWALD_FLAG_VALU_SK | EWALD_FLAG_NO_GRAPH |
-                                       EWALD_FLAG_NO_WORKSPACE)) != 0)
+                                       EWALD_FLAG_NO_WORKSPACE | EWALD_FLAG_ONE_STREAM)) != 0)
         return EWALD_ERR_INVALID_ARG;
     return EWALD_OK;
 }
@@ -812,6 +815,7 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
     // systems at small k); the mixed path rounds phases and coefficients to
     // FP32 in the gather and evaluates the pair functions in FP32.
     // one_stream: everything in order on s (no fork, no events)
+    one_stream = one_stream || (p->prm.flags & EWALD_FLAG_ONE_STREAM) != 0;
     hipStream_t ax = one_stream ? s : p->aux;
     if (!one_stream) {
         if (e == hipSuccess) e = hipEventRecord(p->ev_fork, s);
@@ -862,8 +866,8 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
     // Real space on the caller's stream.
     run(s, KC_BIN, [&] { return launch_bin(s, ca, pos, q, w.cell_of, w.counts, w.qpart, p->status); });
     run(s, KC_SCAN, [&] {
-        return launch_scan(s, ca, w.counts, w.fill, w.cell_start, w.qpart, nqb, w.scalars, w.pitem_cell,
-                           w.pitem_off, w.n_pitems);
+        return launch_scan(s, ca, w.counts, w.fill, w.cell_start, w.qpart, nqb, w.scalars, w.tile_sums,
+                           w.pitem_cell, w.pitem_off, w.n_pitems);
     });
     run(s, KC_SCATTER, [&] { return launch_scatter(s, ca, w.cell_of, w.cell_start, w.fill, w.tmp_idx); });
     run(s, KC_CELLSORT, [&] { return launch_cellsort(s, ca, w.cell_start, w.tmp_idx, pos, q, w.perm, w.pq); });

@@ -30,6 +30,7 @@ FLAG_VALU_GATHER = 1
 FLAG_VALU_SK = 2
 FLAG_NO_GRAPH = 4
 FLAG_NO_WORKSPACE = 8
+FLAG_ONE_STREAM = 16
 SCRATCH_BYTES = 64 << 20  # EWALD_SCRATCH_BYTES
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
@@ -320,7 +321,7 @@ class Plan:
         st = _load().ewald_debug_stats_read(self.handle, int(n), ctypes.byref(out))
         if st != OK:
             raise EwaldError(st, "ewald_debug_stats_read")
-        return {k: int(getattr(out, k)) for k, _ in DebugStats._fields_ if k != "reserved"}
+        return {k: int(getattr(out, k)) for k, _ in DebugStats._fields_ if not k.startswith("reserved")}
 
     def profile(self, enable: bool = True):
         _load().ewald_profile_enable(self.handle, int(bool(enable)))

@@ -40,7 +40,7 @@ def test_status_strings():
 BAD = [
     dict(n_max=0), dict(n_max=(1 << 25) + 1), dict(box_L=0.0), dict(box_L=-1.0), dict(box_L=float("nan")), dict(alpha=0.0),
     dict(alpha=float("inf")), dict(r_c=0.0), dict(r_c=8.5), dict(k_max=0), dict(k_max=ew.K_MAX_LIMIT + 1),
-    dict(precision=2), dict(device=-1), dict(flags=16), dict(flags=-1),
+    dict(precision=2), dict(device=-1), dict(flags=32), dict(flags=-1),
 ]
 
 

@@ -12,6 +12,10 @@ branch it is meant for really ran:
   (the cell sort's global-memory path) and particles with more neighbours
   than the neighbour-list capacity (the direct loop).
 
+Where no list overflows, the number of ordered pairs inside r_c that the
+neighbour lists hold is an integer and is compared exactly with a
+brute-force count over every image.
+
 Bars are those of the other parity tests: relative norms and per-element
 maxima against the FP64 oracle.
 """
@@ -26,6 +30,34 @@ from gpu_helpers import compare
 pytestmark = pytest.mark.gpu
 
 PRECISIONS = ["fp64", "mixed"]
+
+
+def brute_force_pairs(pos, L, rc):
+    """Ordered pairs (i, j, image s) with |r_i - r_j - s| < r_c, i != j or s != 0,
+    for positions in [0, L)^3 and r_c <= L (so |s_a| <= L per axis).  The
+    displacement is formed as the kernel forms it, x_i - (x_j + s).  For
+    r_c <= L/2 only the nearest image per axis can be inside r_c."""
+    x = np.asarray(pos, dtype=np.float64)
+    rc2 = rc * rc
+    n = len(x)
+    total = 0
+    for i0 in range(0, n, 256):
+        xi = x[i0:i0 + 256, None, :]
+        idx = np.arange(i0, min(i0 + 256, n))
+        if rc <= 0.5 * L:
+            raw = xi - x[None, :, :]
+            shifts = [np.where(raw > 0.5 * L, L, np.where(raw < -0.5 * L, -L, 0.0))]
+        else:
+            shifts = [np.broadcast_to(np.array([sx, sy, sz]), (len(idx), n, 3))
+                      for sx in (-L, 0.0, L) for sy in (-L, 0.0, L) for sz in (-L, 0.0, L)]
+        for sh in shifts:
+            d = xi - (x[None, :, :] + sh)
+            r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+            hit = r2 < rc2
+            zero = np.all(sh[np.arange(len(idx)), idx] == 0.0, axis=-1)
+            hit[np.arange(len(idx))[zero], idx[zero]] = False
+            total += int(hit.sum())
+    return total
 
 
 def run_with_stats(pos, q, L, a, rc, K, precision):
@@ -66,6 +98,8 @@ def test_cutoff_equal_to_box(precision):
     got, stats = run_with_stats(pos, q, L, a, L, K, precision)
     compare(got, oracle.energy_forces(pos, q, L, a, L, K, oracle.FAST), precision, "r_c=L")
     assert stats["cells_per_axis"] == 2
+    assert stats["direct_particles"] == 0
+    assert stats["listed_pairs"] == brute_force_pairs(pos, L, L)
 
 
 @pytest.mark.parametrize("precision", PRECISIONS)
