@@ -1,7 +1,7 @@
 """Benchmark: Ewald energy + forces throughput on one MI355X.
 
-Workload: rock-salt lattice of 32^3 sites (N = 32768, L = 32, spacing 1,
-charges +-1, jitter U(-0.1, 0.1)), alpha = 0.7, r_c = 4.5, k_max = 20 -- the
+Headline workload: rock-salt lattice of 32^3 sites (N = 32768, L = 32, spacing
+1, charges +-1, jitter U(-0.1, 0.1)), alpha = 0.7, r_c = 4.5, k_max = 20 -- the
 32^3 NaCl crystal of the paper's strong-scaling study (section 4.2) in reduced
 units.  One step = one complete ewald_energy_forces call (binning, cell list,
 real-space pairs, phase tables, structure factor, reduction, force gather,
@@ -10,10 +10,22 @@ totals) with inputs resident in HBM.
 Prints one JSON line: the mixed-precision throughput as ``value`` (particle
 evaluations per second), the plain-FP64 throughput beside it, p50/p99 latency,
 errors of both paths against the FP64 CPU oracle, the roofline of the dominant
-kernel (per-kernel HIP-event timing on the plan's stream), the oracle's own
-throughput on this host and, under ``serving``, the request server on a mix of
-256 independent electrolyte systems (N = 500 ... 50000, K = 9 ... 41): its
-saturation throughput and p50/p99 latency under Poisson arrivals.
+kernel (per-kernel HIP-event timing on the streams the kernels run on) and the
+oracle's own throughput on this host.  Beside the headline:
+
+* ``configs``: the 8^3 lattice (latency), the 64^3 lattice and the 10^6-ion
+  electrolyte (throughput, p50/p99 latency, per-kernel times and rooflines,
+  errors against the oracle's stored values on 4096 sampled particles);
+* ``rooflines_all``: for every kernel class of the reciprocal space and for the
+  real-space chain, the algorithmic rate (direct-evaluation flop counts) and,
+  for the matrix-core kernels, the rate of the matrix instructions they
+  actually execute, each against its pipe's peak;
+* ``cpu_baselines``: the FP64 oracle on this host's cores at every config
+  (median of 3 runs where that stays short, one run for the 10^6-ion system)
+  and single-threaded at the two smallest, with the CPU model;
+* ``serving``: the request server on a mix of 256 independent electrolyte
+  systems (N = 500 ... 50000, K = 9 ... 41): its saturation throughput and
+  p50/p99 latency under Poisson arrivals.
 """
 import argparse
 import hashlib
@@ -29,29 +41,33 @@ sys.path.insert(0, ROOT)
 METRIC = "Ewald E+F particle-evals/s, mixed vs FP64 at 1e-6 rel force err; p99 latency"
 WORKLOAD = "rocksalt32"
 
-# Algorithmic flops per unit (one particle x one k vector of the half space),
-# counted for a direct evaluation: structure factor 10 (complex phase product 6,
-# charge-weighted complex accumulate 4); force gather 20 (phase 6, Re/Im of
-# exp(i k.r) conj(G) 6, force accumulate 6, potential 2).  Real space: 30 per
-# ordered pair inside the cutoff (plus three special functions).
-FLOPS_PER_UNIT = {"sk": 10.0, "gather": 20.0}
-# Peaks (MI355X, dense): the structure factor runs FP64 matrix-core products
-# (78.6 TFLOP/s) in both precisions; the force gather runs FP32 (157.3) or FP64
-# (78.6) matrix-core products.  VALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA)
-# x 2.4 GHz = 78.6 TFLOP/s for FP64 and for unpacked FP32 (packed dual-FP32 issue
-# is compiled out; the published 157.3 FP32 vector figure counts it).
-PEAK_TFLOPS = 78.6
-PEAK_FP32_PUBLISHED = 157.3
+# Algorithmic flops per unit, counted for a direct evaluation: structure factor
+# 10 per (particle, k in the half space): complex phase product 6 and
+# charge-weighted complex accumulate 4; force gather 20 per (particle, k):
+# phase 6, Re/Im of exp(i k.r) conj(G) 6, force accumulate 6, potential 2; the
+# real-space pair loop 30 per ordered pair inside the cutoff (plus three special
+# functions): displacement 3, |d|^2 5, |d| 1, sqrt(alpha)|d| 1, alpha|d|^2 1,
+# erfc combination 3, q q/r 2, energy 2, force scalar 5, force accumulate 6.
+FLOPS_PER_UNIT = {"sk": 10.0, "gather": 20.0, "realspace": 30.0}
+# Peaks (MI355X, dense): FP64 matrix cores 78.6 TFLOP/s, FP32 matrix cores
+# 157.3; vector ALU 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz =
+# 78.6 TFLOP/s for FP64 and for unpacked FP32 (packed dual-FP32 issue is
+# compiled out; the published 157.3 FP32 vector figure counts it).
+PEAK_VALU = 78.6
 PEAK_MFMA = {"fp64": 78.6, "fp32": 157.3}
+# The real-space chain is the neighbour-list build followed by the pair loop.
+REALSPACE = ("pair_list", "pair")
 
 
-def kernel_bound(kernel, precision):
-    """(bound, peak TFLOP/s) of a hot kernel in the default (matrix-core) plan."""
+def kernel_bound(kernel, precision, stats):
+    """(bound, peak TFLOP/s) of a hot kernel in the plan that ran."""
     if kernel == "sk":
-        return "mfma", PEAK_MFMA["fp64"]
+        return ("mfma", PEAK_MFMA["fp64"]) if stats.get("sk_matrix_cores") else ("alu", PEAK_VALU)
     if kernel == "gather":
-        return "mfma", PEAK_MFMA["fp32" if precision == "mixed" else "fp64"]
-    return "alu", PEAK_TFLOPS
+        if stats.get("gather_matrix_cores"):
+            return "mfma", PEAK_MFMA["fp32" if precision == "mixed" else "fp64"]
+        return "alu", PEAK_VALU
+    return "alu", PEAK_VALU
 
 
 def parse():
@@ -61,6 +77,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--latency-calls", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-large", action="store_true",
+                    help="skip the oracle timings of the 64^3 lattice and the 10^6-ion electrolyte")
+    ap.add_argument("--no-configs", action="store_true", help="headline workload only")
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server measurement")
@@ -88,7 +107,10 @@ def source_hash(kernel):
 def traffic_bytes(kernel, workload, precision):
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE +
     WRITE_SIZE, calibrated against a plain copy), or None when absent or taken
-    on a different kernel source."""
+    on a different kernel source.  The real-space chain sums its two kernels."""
+    if kernel == "realspace":
+        parts = [traffic_bytes(k, workload, precision) for k in REALSPACE]
+        return None if any(p is None for p in parts) else sum(parts)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -130,6 +152,9 @@ def time_steps(plan, pos, q, out, steps, warmup):
 
 
 def kernel_profile(plan, pos, q, out, steps):
+    """Average duration of every kernel class: HIP events around each launch on
+    the stream it is launched on (the reciprocal kernels run on the plan's
+    second stream, concurrently with the real-space ones)."""
     import torch
     plan.profile_reset()
     plan.profile(True)
@@ -141,8 +166,16 @@ def kernel_profile(plan, pos, q, out, steps):
     return {k: {"avg_ms": (v[0] / v[1]) if v[1] else 0.0, "launches": v[1]} for k, v in prof.items()}
 
 
+def pct(sorted_ms, p):
+    return sorted_ms[min(len(sorted_ms) - 1, max(0, int(math.ceil(p * len(sorted_ms))) - 1))]
+
+
 def latencies(plan, pos, q, out, calls):
+    """Synchronised single calls (host wall time), after three warm-up calls."""
     import torch
+    for _ in range(3):
+        plan.energy_forces(pos, q, True, False, out=out)
+    torch.cuda.synchronize()
     lat = []
     for _ in range(calls):
         t = time.perf_counter()
@@ -150,12 +183,121 @@ def latencies(plan, pos, q, out, calls):
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
     lat.sort()
-    return {"p50_ms": lat[len(lat) // 2], "p99_ms": lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
-            "calls": calls}
+    return {"p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "calls": calls}
 
 
-def pct(sorted_ms, p):
-    return sorted_ms[min(len(sorted_ms) - 1, max(0, int(math.ceil(p * len(sorted_ms))) - 1))]
+def rooflines(n, nk, prec, kern, stats, workload):
+    """Per kernel class: algorithmic rate (direct-evaluation flops per launch /
+    average duration) and, for matrix-core kernels, the rate of the matrix
+    instructions executed, each against its pipe's peak."""
+    out = {}
+    units = {"sk": n * nk, "gather": n * nk, "realspace": stats["listed_pairs"]}
+    for k in ("sk", "gather", "realspace"):
+        if k == "realspace":
+            if not all(kern.get(c, {}).get("launches") for c in REALSPACE):
+                continue
+            ms = sum(kern[c]["avg_ms"] for c in REALSPACE)
+        else:
+            if not kern.get(k, {}).get("launches"):
+                continue
+            ms = kern[k]["avg_ms"]
+        flops = FLOPS_PER_UNIT[k] * units[k]
+        ach = flops / (ms * 1e-3) / 1e12
+        bound, peak = kernel_bound(k, prec, stats)
+        r = {"bound": bound, "kernel": k if k != "realspace" else "pair_list+pair", "achieved": ach, "peak": peak,
+             "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_bytes(k, workload, prec), "avg_ms": ms,
+             "algorithmic_flops_per_launch": flops}
+        exe = {"sk": stats.get("sk_mfma_flops", 0), "gather": stats.get("gather_mfma_flops", 0)}.get(k, 0)
+        if exe:
+            r["executed_flops_per_launch"] = exe
+            r["executed_tflops"] = exe / (ms * 1e-3) / 1e12
+            r["executed_frac"] = r["executed_tflops"] / peak
+        out[k] = r
+    return out
+
+
+def golden(name):
+    path = os.path.join(ROOT, "tests", "golden", f"oracle_{name}_s0.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def measure(sysm, prec, steps, warmup, latency_calls, no_graph, want_forces=False):
+    """Throughput, latency, per-kernel profile and branch statistics of one
+    workload in one precision, on a plan sized to its N."""
+    import torch
+    from paper_1708_01135_amd import ewald
+    n = sysm.n
+    dev = torch.device("cuda:0")
+    pos = torch.tensor(sysm.pos, dtype=torch.float64, device=dev)
+    q = torch.tensor(sysm.q, dtype=torch.float64, device=dev)
+    with ewald.Plan(n, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, prec,
+                    flags=ewald.FLAG_NO_GRAPH if no_graph else 0) as plan:
+        out = (torch.empty(5, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
+               torch.empty(n, dtype=torch.float64, device=dev))
+        e, f, g = plan.energy_forces(pos, q, True, True)
+        torch.cuda.synchronize()
+        assert plan.status() == ewald.OK
+        stats = plan.debug_stats(n)
+        res = dict(energy=e.cpu().numpy(), stats=stats)
+        if want_forces:
+            res["forces"], res["dEdq"] = f.cpu().numpy(), g.cpu().numpy()
+        # latency and per-kernel timings first: the throughput window below then
+        # starts on a GPU that is already at its working clocks
+        res["latency"] = latencies(plan, pos, q, out, latency_calls)
+        res["kernels"] = kernel_profile(plan, pos, q, out, max(10, min(steps, 100)))
+        ms = time_steps(plan, pos, q, out, steps, warmup)
+        res["ms"], res["pe_s"] = ms, n / (ms * 1e-3)
+    return res
+
+
+def errors_vs(ref_e, ref_f, got_e, got_f, idx=None):
+    import numpy as np
+    ff = got_f if idx is None else got_f[idx]
+    return {"rel_E": abs(got_e[0] - ref_e[0]) / abs(ref_e[0]),
+            "rel_F": float(np.linalg.norm(ff - ref_f) / np.linalg.norm(ref_f))}
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def time_oracle(sysm, runs, threads=None):
+    """Wall times of `runs` full FP64 oracle evaluations (energy, forces,
+    dE/dq); returns (median seconds, threads used, last result)."""
+    import oracle
+    prev = oracle.num_threads()
+    if threads:
+        oracle.set_num_threads(threads)
+    try:
+        used = oracle.num_threads()
+        ts, ref = [], None
+        for _ in range(runs):
+            t = time.perf_counter()
+            ref = oracle.energy_forces(sysm.pos, sysm.q, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, oracle.FAST)
+            ts.append(time.perf_counter() - t)
+    finally:
+        oracle.set_num_threads(prev)
+    ts.sort()
+    return ts[len(ts) // 2], used, ref
+
+
+def cpu_line(sysm, sec, threads, runs):
+    return {"value": sysm.n / sec, "unit": "particle-evals/s", "cores": threads, "kind": "oracle",
+            "seconds": sec, "sample": f"median of {runs} full FP64 oracle evaluation(s) of the {sysm.n}-ion "
+                                     f"{sysm.name} workload" if runs > 1 else
+            f"one full FP64 oracle evaluation of the {sysm.n}-ion {sysm.name} workload"}
 
 
 def serving(n_systems, passes):
@@ -236,6 +378,16 @@ def serving(n_systems, passes):
     return res
 
 
+def describe(sysm, nk):
+    shape = f"rock-salt {round(sysm.n ** (1 / 3))}^3" if sysm.name.startswith("rocksalt") else "random electrolyte"
+    return (f"{sysm.name}: {shape} N={sysm.n} L={sysm.box_L:g} alpha={sysm.alpha} r_c={sysm.r_c} "
+            f"k_max={sysm.k_max} |K+|={nk}")
+
+
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.calib_copy_mib:
@@ -246,72 +398,90 @@ def main():
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
     import numpy as np
-    import torch
 
     from paper_1708_01135_amd import ewald, workloads
 
+    t_start = time.perf_counter()
     sysm = workloads.make_config(args.workload, 0)
     n = sysm.n
-    dev = torch.device("cuda:0")
-    pos = torch.tensor(sysm.pos, dtype=torch.float64, device=dev)
-    q = torch.tensor(sysm.q, dtype=torch.float64, device=dev)
     nk = ewald.kset_size(sysm.k_max)
-    results = {}
     precisions = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
+    results = {}
     for prec in precisions:
-        plan = ewald.Plan(n, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, prec,
-                          flags=ewald.FLAG_NO_GRAPH if args.no_graph else 0)
-        out = (torch.empty(5, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
-               torch.empty(n, dtype=torch.float64, device=dev))
-        ms = time_steps(plan, pos, q, out, args.steps, args.warmup)
-        e, f, _ = plan.energy_forces(pos, q, True, True)
-        torch.cuda.synchronize()
-        assert plan.status() == ewald.OK
-        kp = kernel_profile(plan, pos, q, out, args.steps)
-        lat = latencies(plan, pos, q, out, args.latency_calls)
-        results[prec] = dict(ms=ms, pe_s=n / (ms * 1e-3), energy=e.cpu().numpy(), forces=f.cpu().numpy(),
-                             kernels=kp, latency=lat)
-        plan.release()
+        log(f"{args.workload} {prec}")
+        results[prec] = measure(sysm, prec, args.steps, args.warmup, args.latency_calls, args.no_graph,
+                                want_forces=True)
 
     # errors against the FP64 CPU oracle, and the oracle's own rate on this host
-    cpu = None
-    errs = {}
+    cpu, cpus, errs = None, {}, {}
     if not args.no_cpu_baseline:
-        import oracle
-        reps, t_tot, ref = 0, 0.0, None
-        while reps < 3 or (t_tot < 10.0 and reps < 20):
-            t = time.perf_counter()
-            ref = oracle.energy_forces(sysm.pos, sysm.q, sysm.box_L, sysm.alpha, sysm.r_c, sysm.k_max, oracle.FAST)
-            t_tot += time.perf_counter() - t
-            reps += 1
-        t_one = t_tot / reps
-        cpu = {"value": n / t_one, "unit": "particle-evals/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"{reps} full FP64 oracle evaluations (energy, forces, dE/dq) of the same "
-                         f"{n}-ion workload, mean {t_one:.3f} s each"}
+        log("oracle on the headline workload")
+        sec, used, ref = time_oracle(sysm, 3)
+        cpu = cpu_line(sysm, sec, used, 3)
+        cpus[sysm.name] = cpu
         for prec, r in results.items():
-            ef, ff = r["energy"], r["forces"]
-            errs[prec] = {"rel_E": abs(ef[0] - ref[0][0]) / abs(ref[0][0]),
-                          "rel_F": float(np.linalg.norm(ff - ref[1]) / np.linalg.norm(ref[1]))}
+            errs[prec] = errors_vs(ref[0], ref[1], r["energy"], r["forces"])
 
-    head = results.get("mixed") or results.get("fp64")
     head_prec = "mixed" if "mixed" in results else "fp64"
-    kern = head["kernels"]
-    dom = max(("sk", "gather", "pair"), key=lambda k: kern.get(k, {}).get("avg_ms", 0.0))
+    head = results[head_prec]
+    per_kernel_roofline = {p: rooflines(n, nk, p, r["kernels"], r["stats"], args.workload)
+                           for p, r in results.items()}
+    roofs = per_kernel_roofline[head_prec]
+    dom = max(roofs, key=lambda k: roofs[k]["avg_ms"]) if roofs else None
+    roof = roofs.get(dom)
 
-    def roofline(k, prec, kp):
-        if k not in FLOPS_PER_UNIT or k not in kp:
-            return None
-        flops = FLOPS_PER_UNIT[k] * n * nk
-        ach = flops / (kp[k]["avg_ms"] * 1e-3) / 1e12
-        bound, peak = kernel_bound(k, prec)
-        return {"bound": bound, "kernel": k, "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
-                "traffic": traffic_bytes(k, args.workload, prec), "avg_ms": kp[k]["avg_ms"],
-                "algorithmic_flops_per_launch": flops}
+    configs = {}
+    if not args.no_configs:
+        for name, steps, calls in (("rocksalt8", 200, 300), ("rocksalt64", 20, 200), ("electrolyte1m", 8, 50)):
+            if name == args.workload:
+                continue
+            t = time.perf_counter()
+            s = workloads.make_config(name, 0)
+            log(f"{name}: generated in {time.perf_counter() - t:.1f} s")
+            snk = ewald.kset_size(s.k_max)
+            g = golden(name)
+            ref = None
+            if name == "rocksalt8":
+                import oracle
+                ref = oracle.energy_forces(s.pos, s.q, s.box_L, s.alpha, s.r_c, s.k_max, oracle.FAST)
+            line = {"workload": describe(s, snk), "n": s.n}
+            for prec in (["fp64", "mixed"] if args.precision == "both" else [args.precision]):
+                log(f"{name} {prec}")
+                r = measure(s, prec, steps, 3, calls, args.no_graph, want_forces=True)
+                entry = {"value": r["pe_s"], "unit": "particle-evals/s", "ms_per_step": r["ms"], "steps": steps,
+                         "latency": r["latency"],
+                         "kernels_ms": {k: round(v["avg_ms"], 5) for k, v in r["kernels"].items()},
+                         "rooflines": rooflines(s.n, snk, prec, r["kernels"], r["stats"], name),
+                         "pairs": r["stats"]["listed_pairs"], "direct_particles": r["stats"]["direct_particles"]}
+                if ref is not None:
+                    entry["errors_vs_oracle"] = errors_vs(ref[0], ref[1], r["energy"], r["forces"])
+                elif g is not None:
+                    idx = np.asarray(g["targets"])
+                    entry["errors_vs_oracle"] = dict(errors_vs(g["energy"], np.asarray(g["forces"]), r["energy"],
+                                                               r["forces"], idx),
+                                                     sample=f"{idx.size} particles stratified over the box")
+                line[prec] = entry
+            if "mixed" in line and "fp64" in line:
+                line["mixed_over_fp64"] = line["mixed"]["value"] / line["fp64"]["value"]
+            if not args.no_cpu_baseline and (name == "rocksalt8" or not args.no_cpu_large):
+                runs = 1 if name == "electrolyte1m" else 3
+                log(f"oracle on {name} ({runs} run(s))")
+                sec, used, _ = time_oracle(s, runs)
+                cpus[name] = cpu_line(s, sec, used, runs)
+            configs[name] = line
+            del s
+        if not args.no_cpu_baseline:
+            # single-threaded oracle at the two smallest configs
+            for name in ("rocksalt8", args.workload):
+                s = workloads.make_config(name, 0)
+                runs = 3 if s.n <= 4096 else 1
+                log(f"single-thread oracle on {name}")
+                sec, used, _ = time_oracle(s, runs, threads=1)
+                cpus[f"{name}_1thread"] = cpu_line(s, sec, used, runs)
 
-    roof = roofline(dom, head_prec, kern)
-    per_kernel_roofline = {p: {k: roofline(k, p, r["kernels"]) for k in FLOPS_PER_UNIT} for p, r in results.items()}
     serve = None
     if not args.no_serving:
+        log("serving mix")
         serve = serving(args.serving_systems, args.serving_passes)
     line = {
         "metric": METRIC,
@@ -326,9 +496,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if head_prec == "mixed" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: rock-salt {round(n ** (1 / 3))}^3 N={n} L={sysm.box_L:g} "
-                               f"alpha={sysm.alpha} r_c={sysm.r_c} k_max={sysm.k_max} |K+|={nk}",
-                   "n": n, "precision": head_prec},
+        "config": {"workload": describe(sysm, nk), "n": n, "precision": head_prec},
         "latency": head["latency"],
         "fp64": None if "fp64" not in results else {
             "value": results["fp64"]["pe_s"], "ms_per_step": results["fp64"]["ms"],
@@ -339,7 +507,11 @@ def main():
         "roofline": roof,
         "rooflines_all": per_kernel_roofline,
         "cpu_baseline": cpu,
+        "cpu_baselines": cpus or None,
+        "host": host_info(),
+        "configs": configs or None,
         "serving": serve,
+        "bench_seconds": round(time.perf_counter() - t_start, 1),
     }
     print(json.dumps(line), flush=True)
 

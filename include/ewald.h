@@ -242,7 +242,9 @@ ewald_status ewald_debug_copy_sk(ewald_plan_t plan, double *re, double *im);
 /* Which branches of the path the plan takes and took (host values).  Filled
  * from the plan's parameters and, after synchronising the plan's stream, from
  * the device state of its last completed evaluation of n particles (n must be
- * that evaluation's particle count).  For tests of the fallback paths. */
+ * that evaluation's particle count).  For tests of the fallback paths, and
+ * for the work the matrix-core kernels execute (their launch shapes for n
+ * particles, counted on the host from the plan's tile layout). */
 typedef struct {
     int64_t max_cell_count;      /* most particles in one real-space cell            */
     int64_t direct_particles;    /* particles whose neighbour list would have passed
@@ -256,6 +258,11 @@ typedef struct {
     int32_t gather_matrix_cores; /* 1: force gather on the matrix cores               */
     int32_t phase_rows;          /* table rows per phase-kernel block                 */
     int32_t reserved;
+    int64_t sk_mfma_flops;       /* flops the matrix-core instructions of one
+                                    structure-factor launch for n particles execute
+                                    (0 on the vector ALUs): 512 per FP64 4x4x4 MFMA   */
+    int64_t gather_mfma_flops;   /* the same for one force-gather launch: 2048 per
+                                    16x16x4 MFMA (FP32 mixed, FP64 plain)             */
 } ewald_debug_stats;
 
 ewald_status ewald_debug_stats_read(ewald_plan_t plan, int64_t n, ewald_debug_stats *out);

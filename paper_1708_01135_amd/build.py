@@ -38,5 +38,20 @@ def build(verbose: bool = False, extra=None) -> str:
     return LIB
 
 
+RSA_LIB = os.path.join(HERE, "librsa_accept.so")
+
+
+def build_host_helpers(verbose: bool = False) -> str:
+    """The input generator's C helper (random sequential addition); no GPU code."""
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-std=c99", "-ffp-contract=off", "-Wall", "-Wextra",
+           "-o", RSA_LIB + ".tmp", os.path.join(HERE, "csrc_host", "rsa_accept.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(RSA_LIB + ".tmp", RSA_LIB)
+    return RSA_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_host_helpers(verbose=True))

@@ -1159,6 +1159,33 @@ ewald_status ewald_debug_stats_read(ewald_plan_t p, int64_t n, ewald_debug_stats
     out->sk_matrix_cores = p->mfma_sk;
     out->gather_matrix_cores = p->mfma_gather;
     out->phase_rows = phase_rows<double>(p->kl.KP);
+    // Matrix-core work per launch, from the launch shapes launch_path uses.
+    const KLayout &kl = p->kl;
+    if (p->mfma_sk) {
+        // every staged sub-chunk of P particles: P / 4 quads x 2 MFMAs (Re U, Im U)
+        // per pair of a of each tile
+        int64_t naps = 0;
+        for (int t : kl.sk_tile_of)
+            if (t >= 0) naps += (kl.row_m[(size_t)t * kSmTileRows] + 2) / 2;
+        const int P = sk_mfma_particles(kl.KP);
+        int64_t c = sk_mfma_target_blocks() / sk_mfma_row_blocks(kl.n_rows);
+        c = std::min<int64_t>(c, p->w.max_chunks);
+        c = std::min<int64_t>(c, (n + P - 1) / P);
+        const int64_t n_chunks = std::max<int64_t>(c, 1), chunk_len = (n + n_chunks - 1) / n_chunks;
+        int64_t subchunks = 0;
+        for (int64_t k = 0; k < n_chunks; ++k) {
+            const int64_t len = std::max<int64_t>(0, std::min<int64_t>(chunk_len, n - k * chunk_len));
+            subchunks += (len + P - 1) / P;
+        }
+        out->sk_mfma_flops = subchunks * (P / 4) * 2 * naps * 512;
+    }
+    if (p->mfma_gather) {
+        // every block of 32 particles: 4 quantities x 2 sub-tiles of 16 per pair of a of every tile
+        int64_t naps = 0;
+        for (const MTile &t : kl.mtiles) naps += t.nap;
+        const int64_t blocks = (n + 31) / 32;
+        out->gather_mfma_flops = blocks * 8 * naps * 2048;
+    }
     return EWALD_OK;
 }
 

@@ -63,7 +63,8 @@ class DebugStats(ctypes.Structure):
     _fields_ = [("max_cell_count", ctypes.c_int64), ("direct_particles", ctypes.c_int64),
                 ("listed_pairs", ctypes.c_int64), ("cells_per_axis", ctypes.c_int32), ("list_capacity", ctypes.c_int32),
                 ("sk_matrix_cores", ctypes.c_int32), ("gather_matrix_cores", ctypes.c_int32),
-                ("phase_rows", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("phase_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sk_mfma_flops", ctypes.c_int64), ("gather_mfma_flops", ctypes.c_int64)]
 
 
 _lib = None
@@ -82,6 +83,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python __graft_entry__.py` "
                           "or `python paper_1708_01135_amd/build.py` (hipcc, gfx950)")
+    # The library links the HIP runtime by its soname (libamdhip64.so.7); the
+    # PyTorch wheel ships its own copy under the same soname.  Loading torch
+    # first makes the library bind to that one runtime, so the device pointers
+    # and streams torch hands over are valid in it (loaded the other way round,
+    # plan creation fails with a device error).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(Params)
     vp = ctypes.c_void_p

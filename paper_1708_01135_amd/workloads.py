@@ -21,8 +21,10 @@ workloads used by the tests and the benchmark.
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import math
+import os
 from typing import Dict, List, Optional, Tuple
 
 import numpy as np
@@ -88,8 +90,27 @@ def rock_salt(n_side: int, jitter: float, seed: int, spacing: float = 1.0,
     return pos, q, L
 
 
+_RSA_LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librsa_accept.so")
+_rsa_fn = None
+
+
+def _rsa_helper():
+    """rsa_accept() from csrc_host/rsa_accept.c when it has been built (it
+    accepts the same candidates as the NumPy loop below, only faster)."""
+    global _rsa_fn
+    if _rsa_fn is None and os.path.exists(_RSA_LIB):
+        lib = ctypes.CDLL(_RSA_LIB)
+        f = lib.rsa_accept
+        f.restype = ctypes.c_int64
+        f.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                      ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64,
+                      ctypes.c_void_p]
+        _rsa_fn = f
+    return _rsa_fn
+
+
 def electrolyte(n: int, density: float, seed: int, d_min: float = 0.8,
-                batch: int = 65536) -> Tuple[np.ndarray, np.ndarray, float]:
+                batch: int = 65536, use_helper: bool = True) -> Tuple[np.ndarray, np.ndarray, float]:
     """Random electrolyte by random sequential addition (RSA).
 
     Candidates are drawn uniformly in the cube of side L = (n/density)^(1/3)
@@ -98,7 +119,8 @@ def electrolyte(n: int, density: float, seed: int, d_min: float = 0.8,
     image).  Batching only vectorises the distance tests: acceptance is still
     decided in draw order, so the result is that of one-at-a-time addition.
     Charges: +1 for the first n//2 accepted ions and -1 for the rest (n even),
-    then shuffled with the same generator.
+    then shuffled with the same generator.  With ``use_helper`` the acceptance
+    loop runs in the C helper when it is built (same result, faster).
     """
     if n % 2:
         raise ValueError("electrolyte needs an even number of ions")
@@ -116,6 +138,17 @@ def electrolyte(n: int, density: float, seed: int, d_min: float = 0.8,
     out = np.empty((n, 3), dtype=np.float64)
     count = 0
     d2 = d_min * d_min
+    helper = _rsa_helper() if use_helper else None
+    if helper is not None:
+        # the same candidate stream, accepted one at a time in C
+        cnt = ctypes.c_int64(0)
+        while cnt.value < n:
+            cand = np.ascontiguousarray(rng.uniform(0.0, L, size=(batch, 3)))
+            helper(L, d_min, g, R, cand.ctypes.data, batch, out.ctypes.data, ctypes.byref(cnt), n,
+                   occ.ctypes.data)
+        q = np.concatenate([np.ones(n // 2), -np.ones(n - n // 2)])
+        rng.shuffle(q)
+        return out, q, L
 
     def min_image(d):
         return d - L * np.round(d / L)
