@@ -87,6 +87,8 @@ def parse():
                     help="plans launch kernel by kernel (no graph replay of repeated evaluations)")
     ap.add_argument("--serving-systems", type=int, default=256)
     ap.add_argument("--serving-passes", type=int, default=3)
+    ap.add_argument("--serving-express-cus", action="store_true",
+                    help="request server whose express stream has compute units of its own")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     return ap.parse_args()
@@ -300,7 +302,7 @@ def cpu_line(sysm, sec, threads, runs):
             f"one full FP64 oracle evaluation of the {sysm.n}-ion {sysm.name} workload"}
 
 
-def serving(n_systems, passes):
+def serving(n_systems, passes, express_cus=False):
     """Request server on independent electrolyte systems (density 0.8, r_c = 4.5,
     alpha r_c^2 = 14.4, K matched to the real-space exponent): saturation throughput
     with every request submitted at once, then Poisson arrivals at fractions of it.
@@ -338,17 +340,38 @@ def serving(n_systems, passes):
     with ewald.Server(n_streams=1, precision="mixed") as srv:
         ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
         t1 = run(srv, ids)
-    with ewald.Server(n_streams=4, precision="mixed") as srv:
+    with ewald.Server(n_streams=4, precision="mixed", express_cus=express_cus) as srv:
         t_add = time.perf_counter()
         ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
         t_add = time.perf_counter() - t_add
-        res["workspace_gb"] = round(srv.stats()["used"] / 1e9, 2)
         res["register_s"] = round(t_add, 2)
         t4 = run(srv, ids)
+        st = srv.stats()
+        res["arena_gb"] = round(st["budget"] / 1e9, 2)
+        res["arena_peak_gb"] = round(st["peak_used"] / 1e9, 2)
+        res["requests_held_for_memory"] = st["held_total"]
         sat = n_systems / t4
+        res["masked_streams"] = st["masked_streams"]
+        res["express_cus"] = bool(express_cus)
         res["saturation"] = {"streams_4": {"systems_per_s": sat, "particle_evals_per_s": ns.sum() / t4,
                                            "tflops_alg": 30.0 * units / t4 / 1e12},
                              "streams_1": {"systems_per_s": n_systems / t1, "particle_evals_per_s": ns.sum() / t1}}
+        # stand-alone latency of every system: one request at a time
+        alone = np.zeros(n_systems)
+        for s in range(n_systems):
+            ts = []
+            for _ in range(3):
+                t = time.perf_counter()
+                srv.wait(srv.submit(ids[s], pos[s], q[s], out=outs[s]))
+                ts.append(time.perf_counter() - t)
+            alone[s] = sorted(ts)[1] * 1e3
+        buckets = [(500, 2000), (2000, 5000), (5000, 20000), (20000, 50001)]
+        res["buckets"] = [f"{lo}-{hi - 1 if hi == 50001 else hi}" for lo, hi in buckets]
+        res["alone_p50_ms"] = {}
+        for (lo, hi), name in zip(buckets, res["buckets"]):
+            sel = np.sort(alone[(ns >= lo) & (ns < hi)])
+            if sel.size:
+                res["alone_p50_ms"][name] = float(sel[sel.size // 2])
         rng = np.random.default_rng(1000)
         res["poisson"] = []
         for frac in (0.25, 0.5, 0.7, 0.9):
@@ -367,10 +390,19 @@ def serving(n_systems, passes):
                 _, _, td = srv.wait(t)
                 lat.append((td - ta) * 1e3)
                 t_end = max(t_end, td)
+            lat_arr = np.array(lat)
+            ratio = lat_arr / alone[seq]
+            per_bucket = {}
+            for (lo, hi), name in zip(buckets, res["buckets"]):
+                m = (ns[seq] >= lo) & (ns[seq] < hi)
+                if m.any():
+                    lb, rb = sorted(lat_arr[m]), sorted(ratio[m])
+                    per_bucket[name] = {"requests": int(m.sum()), "p50_ms": pct(lb, 0.5), "p99_ms": pct(lb, 0.99),
+                                        "p99_over_alone": pct(rb, 0.99)}
             lat.sort()
             res["poisson"].append({"load": frac, "rate_per_s": rate, "requests": int(seq.size),
                                    "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99), "max_ms": lat[-1],
-                                   "achieved_per_s": seq.size / (t_end - t0)})
+                                   "achieved_per_s": seq.size / (t_end - t0), "by_size": per_bucket})
             print(f"serving load {frac}: p50 {pct(lat, 0.5):.3f} ms p99 {pct(lat, 0.99):.3f} ms", file=sys.stderr,
                   flush=True)
         for i in ids:
@@ -482,7 +514,7 @@ def main():
     serve = None
     if not args.no_serving:
         log("serving mix")
-        serve = serving(args.serving_systems, args.serving_passes)
+        serve = serving(args.serving_systems, args.serving_passes, args.serving_express_cus)
     line = {
         "metric": METRIC,
         "value": head["pe_s"],

@@ -197,6 +197,30 @@ ewald_status ewald_energy(ewald_plan_t plan, int64_t n, const double *pos, const
 ewald_status ewald_energy_backward(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
                                    const double *grad_energy, double *energy, double *grad_pos, double *grad_q);
 
+/* Bytes of the per-evaluation buffers (cell list, neighbour lists, phase
+ * tables, structure-factor partials, gather partials, counters) of one
+ * evaluation of n particles on this plan: the workspace that
+ * ewald_energy_forces_ws() takes.  Host only; 0 for a NULL plan or n outside
+ * 1 .. n_max. */
+size_t ewald_eval_workspace_bytes(ewald_plan_t plan, int64_t n);
+
+/* ewald_energy_forces() with its per-evaluation buffers in caller memory.
+ *   workspace        device, 256-byte aligned, at least
+ *                    ewald_eval_workspace_bytes(plan, n) bytes; the call's
+ *                    kernels use it until the call's work on the plan's stream
+ *                    has completed (the caller may reuse it after that).
+ *   workspace_bytes  its size.
+ * Same results, bit for bit, as ewald_energy_forces() on the same plan (the
+ * same kernels with the same launch shapes).  Allocates nothing; launches
+ * kernel by kernel (no graph replay, no profiling); the counters that must
+ * start at zero are cleared in the workspace by a fill kernel.  The plan may
+ * have been made with EWALD_FLAG_NO_WORKSPACE.  Errors as
+ * ewald_energy_forces(), plus INVALID_ARG for a NULL or misaligned workspace
+ * and CAPACITY for one that is too small (nothing enqueued). */
+ewald_status ewald_energy_forces_ws(ewald_plan_t plan, int64_t n, const double *pos, const double *q,
+                                    double *energy, double *forces, double *dEdq, void *workspace,
+                                    size_t workspace_bytes);
+
 /* Allocation-free variant of ewald_energy_forces(), for callers that cannot
  * allocate device memory while they evaluate: code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,

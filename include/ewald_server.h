@@ -4,22 +4,42 @@
  *
  * Each registered system is one plan of the evaluation in ewald.h (the
  * real-space, reciprocal-space, self and background terms of Saunders, Grant
- * & Mueller, section 3); its workspace (cell lists, phase tables, structure
- * factor) stays resident on the device between requests.  A request is one
- * energy/force evaluation of a registered system.  A native dispatcher thread
- * owned by the server takes requests in submission order and enqueues each on
- * one of the server's streams, so that small systems run beside large ones:
- *   - a system's requests are serialised (they share its workspace): while one
- *     is in flight, the next goes to the same stream;
- *   - otherwise the stream with the least outstanding work (estimated from N
- *     and the k-set size) is taken.
+ * & Mueller, section 3); its constant tables (k-set layout, C_k) stay
+ * resident on the device between requests.  A request is one energy/force
+ * evaluation of a registered system.  A native dispatcher thread owned by the
+ * server takes requests in submission order and enqueues each on one of the
+ * server's streams, so that small systems run beside large ones:
+ *   - a system's requests start in submission order, and while one is in
+ *     flight the next goes to the same stream (its plan is not re-entrant);
+ *   - otherwise a small request (estimated work below that of about a
+ *     5,000-ion electrolyte at the serving mix's density) goes to the express
+ *     stream, stream 0, so that it never queues behind a large one, and any
+ *     other request to the stream with the least outstanding estimated work
+ *     among the rest (with one stream, everything goes to it);
+ *   - a stream takes at most 2 requests at a time; the rest wait in the
+ *     dispatcher, where a small request that arrives later still passes them;
+ *   - the systems' plans run their real- and reciprocal-space chains on the
+ *     request's stream (EWALD_FLAG_ONE_STREAM); requests in flight on
+ *     different streams overlap instead;
+ *   - with EWALD_SERVER_FLAG_EXPRESS_CUS, more than one stream and a 256-CU
+ *     device, the streams are created with CU masks: the express stream runs
+ *     on 16 compute units (two per XCD) and the bulk streams on the other
+ *     240, so a small request never waits for the workgroups of a large one
+ *     to leave a CU (throughput of large requests drops by about the share of
+ *     the reserved CUs).
  * Completion is detected by polling one event per request; the request's
  * latency is measured on the server's monotonic clock from its submission to
  * the moment the dispatcher observes its completion.
  *
- * Admission: a system is admitted only if its plan workspace
- * (ewald_plan_workspace_bytes) fits the budget still free; nothing is
- * allocated otherwise (EWALD_ERR_ADMISSION).
+ * Admission by HBM footprint, per request: the server holds one device arena
+ * of hbm_budget bytes; a request is started only when its per-evaluation
+ * buffers (ewald_eval_workspace_bytes for its n: cell list, neighbour lists,
+ * phase tables, partial sums) fit in the arena, and they return to the arena
+ * when it completes.  A request that does not fit is held, not refused: it
+ * starts as soon as completions free enough memory.  Later requests may start
+ * before a held one while it has waited less than 20 ms; after that nothing
+ * passes it.  A system whose largest request (n_max) could never fit the
+ * arena is refused at registration (EWALD_ERR_ADMISSION).
  *
  * Thread safety: every entry point may be called from any host thread.  The
  * caller guarantees that a request's inputs are complete on the device when
@@ -46,9 +66,11 @@ typedef struct ewald_server_s *ewald_server_t;
  *   device      HIP device ordinal.
  *   n_streams   streams requests are spread over, 1 <= n_streams <= 16.
  *   precision   EWALD_PRECISION_FP64 or EWALD_PRECISION_MIXED, for every system.
- *   flags       reserved, must be 0.
- *   hbm_budget  bytes of plan workspace the server may hold; 0 means 90 % of
- *               the device memory free when the server is created. */
+ *   flags       0, or EWALD_SERVER_FLAG_EXPRESS_CUS: the express stream gets
+ *               compute units of its own (see below).
+ *   hbm_budget  bytes of the device arena for the buffers of requests in
+ *               flight, allocated when the server is created; 0 means 90 % of
+ *               the free device memory, at most 8 GiB. */
 typedef struct {
     int32_t device;
     int32_t n_streams;
@@ -57,14 +79,20 @@ typedef struct {
     uint64_t hbm_budget;
 } ewald_server_params;
 
+#define EWALD_SERVER_FLAG_EXPRESS_CUS 1
+
 /* Counters of a server (host values). */
 typedef struct {
     int64_t systems;       /* registered systems                       */
     int64_t submitted;     /* requests accepted by ewald_server_submit */
     int64_t completed;     /* requests whose completion was observed   */
     int64_t in_flight;     /* enqueued on a stream, not yet completed  */
-    uint64_t budget;       /* admission budget, bytes                  */
-    uint64_t used;         /* workspace of the registered systems      */
+    uint64_t budget;       /* arena bytes                              */
+    uint64_t used;         /* arena bytes held by requests in flight   */
+    uint64_t peak_used;    /* most arena bytes held at once            */
+    int64_t held;          /* requests now waiting for arena memory    */
+    int64_t held_total;    /* requests that had to wait for memory     */
+    int64_t masked_streams; /* bulk streams created with a CU mask     */
 } ewald_server_stats;
 
 /* Create a server and start its dispatcher thread.  *out is NULL on failure.
@@ -72,20 +100,22 @@ typedef struct {
 ewald_status ewald_server_create(const ewald_server_params *params, ewald_server_t *out);
 
 /* Register a system: box side, splitting exponent, cutoffs and capacity as in
- * ewald_params (its precision, device and stream fields are ignored: the
- * server's are used).  On success *system_id receives a non-negative id.
- * Errors: INVALID_ARG (bad parameters), ADMISSION (workspace above the free
- * budget; nothing allocated), OUT_OF_MEMORY, DEVICE. */
+ * ewald_params (its precision, device, stream and flags fields are ignored:
+ * the server's are used).  Builds the system's plan without a workspace.  On
+ * success *system_id receives a non-negative id.  Errors: INVALID_ARG (bad
+ * parameters), ADMISSION (a request of n_max particles could never fit the
+ * arena; nothing kept), OUT_OF_MEMORY, DEVICE. */
 ewald_status ewald_server_add_system(ewald_server_t server, const ewald_params *params, int32_t *system_id);
 
-/* Wait for the system's requests, release its plan and return its workspace
- * to the budget.  Errors: INVALID_ARG (unknown id). */
+/* Wait for the system's requests, then release its plan.  Errors:
+ * INVALID_ARG (unknown id). */
 ewald_status ewald_server_remove_system(ewald_server_t server, int32_t system_id);
 
 /* Submit one evaluation of a registered system; arguments as
  * ewald_energy_forces() (device pointers, n <= the system's n_max).  Returns
- * at once; *ticket identifies the request for ewald_server_wait().
- * Errors (nothing submitted): INVALID_ARG, CAPACITY. */
+ * at once, also when the request has to wait for arena memory; *ticket
+ * identifies the request for ewald_server_wait().  Errors (nothing
+ * submitted): INVALID_ARG, CAPACITY. */
 ewald_status ewald_server_submit(ewald_server_t server, int32_t system_id, int64_t n, const double *pos,
                                  const double *q, double *energy, double *forces, double *dEdq, int64_t *ticket);
 

@@ -1002,6 +1002,52 @@ ewald_status ewald_energy_forces(ewald_plan_t p, int64_t n, const double *pos, c
     return run_path(p, n, pos, q, energy, forces, dEdq, nullptr, false);
 }
 
+size_t ewald_eval_workspace_bytes(ewald_plan_t p, int64_t n)
+{
+    if (!p || n < 1 || n > p->prm.n_max) return 0;
+    Sizes z;
+    compute_sizes(p->prm, p->kl, p->nc, n, z);
+    return z.work;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One evaluation whose per-evaluation buffers are carved from `base` (sized for
+// n by compute_sizes): the counters and padding that must start at zero are
+// cleared first, then the kernels are launched one by one.
+ewald_status run_in_buffers(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy,
+                            double *forces, double *dEdq, void *base, const Sizes &z)
+{
+    DeviceGuard dg(p->device);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    Work w;
+    carve_work(static_cast<char *>(base), z, w);
+    if (launch_zero(p->stream, base, zeroed_bytes(z)) != hipSuccess) {
+        (void)hipGetLastError();
+        return EWALD_ERR_DEVICE;
+    }
+    p->last_graph = false;  // this call's join event marks its completion
+    return launch_path(p, w, p->stream, false, n, pos, q, energy, forces, dEdq, nullptr, false, false);
+}
+
+}  // namespace
+
+extern "C" {
+
+ewald_status ewald_energy_forces_ws(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy,
+                                    double *forces, double *dEdq, void *workspace, size_t workspace_bytes)
+{
+    if (!p || !pos || !q || !energy || n < 1 || !workspace || (reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+        return EWALD_ERR_INVALID_ARG;
+    if (n > p->prm.n_max) return EWALD_ERR_CAPACITY;
+    Sizes z;
+    compute_sizes(p->prm, p->kl, p->nc, n, z);
+    if (z.work > workspace_bytes) return EWALD_ERR_CAPACITY;
+    return run_in_buffers(p, n, pos, q, energy, forces, dEdq, workspace, z);
+}
+
 ewald_status ewald_energy_forces_noalloc(ewald_plan_t p, int64_t n, const double *pos, const double *q,
                                          double *energy, double *forces, double *dEdq)
 {
@@ -1011,17 +1057,8 @@ ewald_status ewald_energy_forces_noalloc(ewald_plan_t p, int64_t n, const double
     compute_sizes(p->prm, p->kl, p->nc, n, z);
     if (z.work > EWALD_SCRATCH_BYTES) return EWALD_ERR_SCRATCH;
     if (!p->scratch) return EWALD_ERR_DEVICE;
-    DeviceGuard dg(p->device);
-    if (!dg.ok()) return EWALD_ERR_DEVICE;
-    Work w;
-    carve_work(static_cast<char *>(p->scratch), z, w);
     // the array keeps whatever the last call on this device left in it
-    if (launch_zero(p->stream, p->scratch, zeroed_bytes(z)) != hipSuccess) {
-        (void)hipGetLastError();
-        return EWALD_ERR_DEVICE;
-    }
-    p->last_graph = false;  // this call's join event marks its completion
-    return launch_path(p, w, p->stream, false, n, pos, q, energy, forces, dEdq, nullptr, false, false);
+    return run_in_buffers(p, n, pos, q, energy, forces, dEdq, p->scratch, z);
 }
 
 ewald_status ewald_energy(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy)

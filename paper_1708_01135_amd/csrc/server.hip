@@ -1,6 +1,7 @@
 // Request loop serving many independent Ewald systems on one GPU (C ABI in
 // include/ewald_server.h).  Built only on the public plan ABI of ewald.h:
-// every evaluation is one ewald_energy_forces() call on the system's plan,
+// every evaluation is one ewald_energy_forces_ws() call on the system's plan,
+// with its per-evaluation buffers in a block of the server's device arena,
 // enqueued by a dispatcher thread on one of the server's streams.
 #include <hip/hip_runtime.h>
 
@@ -8,6 +9,8 @@
 #include <condition_variable>
 #include <ctime>
 #include <deque>
+#include <list>
+#include <map>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -19,6 +22,32 @@
 namespace {
 
 constexpr int kMaxStreams = 16;
+// Requests whose estimated work is below this go to the express stream
+// (stream 0, when the server has more than one), so that they never queue
+// behind a large request: about a 5,000-ion electrolyte at the serving mix's
+// density and cutoffs (30 flops per particle and k vector, 40 per pair).
+constexpr double kExpressCost = 3.0e9;
+// A held request (its workspace did not fit) that has waited this long stops
+// later requests of its class (express or bulk) from taking arena memory
+// before it.
+constexpr double kMaxHoldBypass = 0.020;
+// Requests in flight per stream: enough queued work to keep the GPU busy;
+// the rest wait in the dispatcher's pending list, where a small request that
+// arrives later can still pass them (and their workspace is not yet taken).
+constexpr int kMaxInFlightPerStream = 2;
+constexpr size_t kArenaAlign = 256;
+// With EWALD_SERVER_FLAG_EXPRESS_CUS: compute units of the express stream, two
+// on each of the 8 XCDs of a 256-CU part, bits 32 g + g and 32 g + g + 8 for
+// g = 0..7, which fall two on every XCD whether the mask numbers CUs XCD by
+// XCD (32 each) or interleaves them over the XCDs.  The bulk streams get the
+// other CUs, so neither class waits for the other's workgroups.
+constexpr int kCusExpected = 256;
+inline bool reserved_cu(int i)
+{
+    const int g = i / 32, h = i % 32;
+    return h == g || h == g + 8;
+}
+constexpr uint64_t kDefaultArenaCap = (uint64_t)8 << 30;
 
 double now_s()
 {
@@ -29,13 +58,14 @@ double now_s()
 
 struct System {
     ewald_plan_t plan = nullptr;
-    size_t bytes = 0;
+    size_t bytes = 0;  // workspace of a request of n_max particles
     int64_t n_max = 0;
     double cost_per_particle = 0.0;  // relative work estimate of one request per particle
     int stream = -1;                 // stream of its requests in flight (dispatcher)
     int queued = 0;                  // submitted, not yet enqueued      (under the lock)
     int in_flight = 0;               // enqueued, not yet completed      (under the lock)
     bool removing = false;           // no further submissions           (under the lock)
+    int64_t hold_pass = -1;          // pass of start_pending that held one of its requests
 };
 
 struct Request {
@@ -46,10 +76,68 @@ struct Request {
     double *energy = nullptr, *forces = nullptr, *dEdq = nullptr;
     double t_submit = 0.0, t_done = 0.0;
     double cost = 0.0;
+    size_t ws_bytes = 0, ws_off = 0;  // its block of the arena
     int stream = -1;
     hipEvent_t ev = nullptr;
     ewald_status status = EWALD_OK;
-    bool done = false, waited = false;
+    bool done = false, waited = false, held = false;
+};
+
+// First-fit allocator over one device allocation (host bookkeeping only; used
+// by the dispatcher thread alone).
+class Arena {
+  public:
+    void reset(char *base, size_t size)
+    {
+        base_ = base;
+        size_ = size;
+        free_.clear();
+        if (size) free_[0] = size;
+        used_ = peak_ = 0;
+    }
+    char *base() const { return base_; }
+    size_t size() const { return size_; }
+    size_t used() const { return used_; }
+    size_t peak() const { return peak_; }
+    static size_t round(size_t b) { return (b + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+    bool alloc(size_t bytes, size_t &off)
+    {
+        bytes = round(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            off = it->first;
+            const size_t rest = it->second - bytes;
+            free_.erase(it);
+            if (rest) free_[off + bytes] = rest;
+            used_ += bytes;
+            peak_ = std::max(peak_, used_);
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        bytes = round(bytes);
+        used_ -= bytes;
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+  private:
+    char *base_ = nullptr;
+    size_t size_ = 0, used_ = 0, peak_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
 };
 
 class DeviceGuard {
@@ -81,13 +169,20 @@ struct ewald_server_s {
     std::condition_variable cv_work, cv_done;
     std::vector<System *> systems;  // by id, nullptr once removed
     std::unordered_map<int64_t, Request *> requests;
-    std::deque<Request *> queue;  // submitted, not yet enqueued
+    std::deque<Request *> queue;  // submitted, not yet seen by the dispatcher
     int64_t next_ticket = 0, submitted = 0, completed = 0, in_flight = 0;
-    uint64_t budget = 0, used = 0;
+    int64_t held = 0, held_total = 0;  // waiting for arena memory now / ever
+    uint64_t budget = 0, used = 0, peak_used = 0;
     bool stop = false;
+    void *arena_mem = nullptr;
     // dispatcher-only state
+    Arena arena;
+    std::list<Request *> pending;  // seen, not yet enqueued (in submission order)
+    int64_t pass = 0;              // start_pending passes
+    int masked = 0;                // bulk streams created with the CU mask
     std::vector<Request *> flight;
     std::vector<double> load;
+    std::vector<int> stream_flight;  // requests in flight per stream
     std::vector<hipEvent_t> events;
     std::thread worker;
 };
@@ -106,23 +201,38 @@ hipEvent_t take_event(ewald_server_s *s)
     return e;
 }
 
-// Enqueue one request: its system's stream while the system has work in
-// flight (requests of a system share its workspace), else the stream with
-// the least outstanding estimated work.
-void enqueue(ewald_server_s *s, Request *r)
+bool is_express(const ewald_server_s *s, const Request *r)
+{
+    return s->streams.size() > 1 && r->cost < kExpressCost;
+}
+
+// The stream a request would go to now, or -1 if it has to wait for a slot:
+// its system's stream while the system has work in flight (the plan is not
+// re-entrant), the express stream for a small request, else the bulk stream
+// with the least outstanding estimated work; a stream takes at most
+// kMaxInFlightPerStream requests at a time.
+int pick_stream(const ewald_server_s *s, const Request *r)
+{
+    const int ns = (int)s->streams.size();
+    auto open = [&](int i) { return s->stream_flight[i] < kMaxInFlightPerStream; };
+    if (r->sys->in_flight > 0) return open(r->sys->stream) ? r->sys->stream : -1;
+    if (is_express(s, r)) return open(0) ? 0 : -1;
+    int st = -1;
+    for (int i = ns > 1 ? 1 : 0; i < ns; ++i)
+        if (open(i) && (st < 0 || s->load[i] < s->load[st])) st = i;
+    return st;
+}
+
+// Enqueue one request whose workspace block is reserved on stream st.
+void enqueue(ewald_server_s *s, Request *r, int st)
 {
     System *y = r->sys;
-    int st = 0;
-    if (y->in_flight > 0) {
-        st = y->stream;
-    } else {
-        for (int i = 1; i < (int)s->streams.size(); ++i)
-            if (s->load[i] < s->load[st]) st = i;
-    }
     hipEvent_t ev = take_event(s);
     ewald_status rc = ev ? EWALD_OK : EWALD_ERR_DEVICE;
     if (rc == EWALD_OK) rc = ewald_plan_set_stream(y->plan, s->streams[st]);
-    if (rc == EWALD_OK) rc = ewald_energy_forces(y->plan, r->n, r->pos, r->q, r->energy, r->forces, r->dEdq);
+    if (rc == EWALD_OK)
+        rc = ewald_energy_forces_ws(y->plan, r->n, r->pos, r->q, r->energy, r->forces, r->dEdq,
+                                    s->arena.base() + r->ws_off, r->ws_bytes);
     if (rc == EWALD_OK && hipEventRecord(ev, s->streams[st]) != hipSuccess) {
         (void)hipGetLastError();
         rc = EWALD_ERR_DEVICE;
@@ -131,6 +241,8 @@ void enqueue(ewald_server_s *s, Request *r)
     y->queued -= 1;
     if (rc != EWALD_OK) {
         if (ev) s->events.push_back(ev);
+        s->arena.release(r->ws_off, r->ws_bytes);
+        s->used = s->arena.used();
         r->status = rc;
         r->t_done = now_s();
         r->done = true;
@@ -144,7 +256,59 @@ void enqueue(ewald_server_s *s, Request *r)
     y->in_flight += 1;
     s->in_flight += 1;
     s->load[st] += r->cost;
+    s->stream_flight[st] += 1;
     s->flight.push_back(r);
+}
+
+// Starts pending requests, in submission order, when their stream has a slot
+// and their workspace fits the arena.  One that does not fit is held (it stays
+// pending) and later ones may go ahead, until it has waited kMaxHoldBypass:
+// then nothing of its class (express or bulk) behind it starts before it does.
+// A system's requests start in submission order.  Returns whether any started.
+bool start_pending(ewald_server_s *s)
+{
+    bool any = false, blocked[2] = {false, false};
+    const double now = now_s();
+    const int64_t pass = ++s->pass;
+    for (auto it = s->pending.begin(); it != s->pending.end();) {
+        Request *r = *it;
+        const int cls = is_express(s, r) ? 0 : 1;
+        if (r->sys->hold_pass == pass || blocked[cls]) {
+            r->sys->hold_pass = pass;
+            ++it;
+            continue;
+        }
+        const int st = pick_stream(s, r);
+        if (st < 0) {  // no slot now; later requests of other systems may have one
+            r->sys->hold_pass = pass;
+            ++it;
+            continue;
+        }
+        size_t off = 0;
+        if (s->arena.alloc(r->ws_bytes, off)) {
+            r->ws_off = off;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                if (r->held) s->held -= 1;
+                s->used = s->arena.used();
+                s->peak_used = s->arena.peak();
+            }
+            it = s->pending.erase(it);
+            enqueue(s, r, st);
+            any = true;
+            continue;
+        }
+        r->sys->hold_pass = pass;
+        if (!r->held) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            r->held = true;
+            s->held += 1;
+            s->held_total += 1;
+        }
+        if (now - r->t_submit > kMaxHoldBypass) blocked[cls] = true;
+        ++it;
+    }
+    return any;
 }
 
 // Completion of requests in flight; returns whether any completed.
@@ -164,7 +328,10 @@ bool poll_flight(ewald_server_s *s)
             std::lock_guard<std::mutex> lk(s->mu);
             s->events.push_back(r->ev);
             r->ev = nullptr;
+            s->arena.release(r->ws_off, r->ws_bytes);
+            s->used = s->arena.used();
             s->load[r->stream] = std::max(0.0, s->load[r->stream] - r->cost);
+            s->stream_flight[r->stream] -= 1;
             r->t_done = t;
             if (e != hipSuccess) r->status = EWALD_ERR_DEVICE;
             r->done = true;
@@ -183,21 +350,19 @@ bool poll_flight(ewald_server_s *s)
 void dispatcher(ewald_server_s *s)
 {
     (void)hipSetDevice(s->prm.device);
-    std::vector<Request *> batch;
     for (;;) {
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            if (s->queue.empty() && s->flight.empty()) {
+            if (s->queue.empty() && s->flight.empty() && s->pending.empty()) {
                 s->cv_work.wait(lk, [s] { return s->stop || !s->queue.empty(); });
                 if (s->queue.empty()) break;  // stopped and drained
             }
-            batch.assign(s->queue.begin(), s->queue.end());
+            s->pending.insert(s->pending.end(), s->queue.begin(), s->queue.end());
             s->queue.clear();
         }
-        bool progress = !batch.empty();
-        for (Request *r : batch) enqueue(s, r);
-        batch.clear();
-        progress = poll_flight(s) || progress;
+        // completions first: they return arena memory to held requests
+        bool progress = poll_flight(s);
+        progress = start_pending(s) || progress;
         if (!progress) std::this_thread::yield();
     }
 }
@@ -218,7 +383,8 @@ ewald_status ewald_server_create(const ewald_server_params *params, ewald_server
 {
     if (!out) return EWALD_ERR_INVALID_ARG;
     *out = nullptr;
-    if (!params || params->n_streams < 1 || params->n_streams > kMaxStreams || params->flags != 0 ||
+    if (!params || params->n_streams < 1 || params->n_streams > kMaxStreams ||
+        (params->flags & ~EWALD_SERVER_FLAG_EXPRESS_CUS) != 0 ||
         params->device < 0 ||
         (params->precision != EWALD_PRECISION_FP64 && params->precision != EWALD_PRECISION_MIXED))
         return EWALD_ERR_INVALID_ARG;
@@ -240,15 +406,45 @@ ewald_status ewald_server_create(const ewald_server_params *params, ewald_server
             delete s;
             return EWALD_ERR_DEVICE;
         }
-        s->budget = (uint64_t)(0.9 * (double)free_b);
+        s->budget = std::min<uint64_t>((uint64_t)(0.9 * (double)free_b), kDefaultArenaCap);
     }
+    s->budget = s->budget / kArenaAlign * kArenaAlign;
+    if (s->budget == 0 || hipMalloc(&s->arena_mem, s->budget) != hipSuccess) {
+        (void)hipGetLastError();
+        delete s;
+        return EWALD_ERR_OUT_OF_MEMORY;
+    }
+    s->arena.reset(static_cast<char *>(s->arena_mem), s->budget);
     bool ok = hipStreamCreateWithFlags(&s->setup, hipStreamNonBlocking) == hipSuccess;
+    // with EWALD_SERVER_FLAG_EXPRESS_CUS and more than one stream, the express
+    // stream (0) runs on the reserved CUs and the bulk streams on the others,
+    // so that a small request always finds free CUs beside large ones
+    int n_cus = 0;
+    if (hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, params->device) != hipSuccess) {
+        (void)hipGetLastError();
+        n_cus = 0;
+    }
+    const bool reserve = params->n_streams > 1 && n_cus == kCusExpected && (params->flags & EWALD_SERVER_FLAG_EXPRESS_CUS);
+    std::vector<uint32_t> bulk_mask((size_t)(kCusExpected + 31) / 32, 0u), express_mask(bulk_mask.size(), 0u);
+    for (int i = 0; i < kCusExpected; ++i) {
+        if (reserved_cu(i))
+            express_mask[(size_t)i / 32] |= 1u << (i % 32);
+        else
+            bulk_mask[(size_t)i / 32] |= 1u << (i % 32);
+    }
     for (int i = 0; ok && i < params->n_streams; ++i) {
         hipStream_t st = nullptr;
-        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        const std::vector<uint32_t> &mask = i == 0 ? express_mask : bulk_mask;
+        if (reserve && hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()) == hipSuccess) {
+            s->masked += 1;
+        } else {
+            (void)hipGetLastError();
+            ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        }
         if (ok) s->streams.push_back(st);
     }
     s->load.assign(s->streams.size(), 0.0);
+    s->stream_flight.assign(s->streams.size(), 0);
     if (ok) {
         try {
             s->worker = std::thread(dispatcher, s);
@@ -260,6 +456,7 @@ ewald_status ewald_server_create(const ewald_server_params *params, ewald_server
         (void)hipGetLastError();
         for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
         if (s->setup) (void)hipStreamDestroy(s->setup);
+        (void)hipFree(s->arena_mem);
         delete s;
         return EWALD_ERR_DEVICE;
     }
@@ -275,22 +472,22 @@ ewald_status ewald_server_add_system(ewald_server_t s, const ewald_params *param
     p.precision = s->prm.precision;
     p.device = s->prm.device;
     p.stream = s->setup;
+    // requests take their buffers from the arena, and run wholly on the stream
+    // the dispatcher gives them (so that its CU mask covers every kernel)
+    p.flags = EWALD_FLAG_NO_WORKSPACE | EWALD_FLAG_ONE_STREAM;
     if (ewald_params_validate(&p) != EWALD_OK) return EWALD_ERR_INVALID_ARG;
-    const size_t bytes = ewald_plan_workspace_bytes(&p);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->used + bytes > s->budget) return EWALD_ERR_ADMISSION;
-        s->used += bytes;  // reserved while the plan is built
-    }
     System *y = new (std::nothrow) System();
     ewald_status rc = y ? ewald_plan(&p, &y->plan) : EWALD_ERR_OUT_OF_MEMORY;
     if (rc != EWALD_OK) {
         delete y;
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->used -= bytes;
         return rc;
     }
-    y->bytes = bytes;
+    y->bytes = ewald_eval_workspace_bytes(y->plan, p.n_max);
+    if (Arena::round(y->bytes) > s->budget) {  // a request of n_max could never run
+        ewald_release(y->plan);
+        delete y;
+        return EWALD_ERR_ADMISSION;
+    }
     y->n_max = p.n_max;
     // work of one request per particle: the two reciprocal sweeps (structure
     // factor and gather, ~30 flops per k vector) and the pairs inside r_c
@@ -315,7 +512,6 @@ ewald_status ewald_server_remove_system(ewald_server_t s, int32_t id)
         y->removing = true;
         s->cv_done.wait(lk, [y] { return y->queued == 0 && y->in_flight == 0; });
         s->systems[id] = nullptr;
-        s->used -= y->bytes;
     }
     ewald_release(y->plan);
     delete y;
@@ -346,6 +542,7 @@ ewald_status ewald_server_submit(ewald_server_t s, int32_t id, int64_t n, const 
             return EWALD_ERR_CAPACITY;
         }
         r->sys = y;
+        r->ws_bytes = ewald_eval_workspace_bytes(y->plan, n);
         r->cost = y->cost_per_particle * (double)n + 2.0e6;
         r->ticket = s->next_ticket++;
         r->t_submit = now_s();
@@ -422,6 +619,10 @@ ewald_status ewald_server_get_stats(ewald_server_t s, ewald_server_stats *out)
     out->in_flight = s->in_flight;
     out->budget = s->budget;
     out->used = s->used;
+    out->peak_used = s->peak_used;
+    out->held = s->held;
+    out->held_total = s->held_total;
+    out->masked_streams = s->masked;
     return EWALD_OK;
 }
 
@@ -444,6 +645,7 @@ void ewald_server_destroy(ewald_server_t s)
     for (hipEvent_t e : s->events) (void)hipEventDestroy(e);
     for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
     if (s->setup) (void)hipStreamDestroy(s->setup);
+    (void)hipFree(s->arena_mem);
     delete s;
 }
 

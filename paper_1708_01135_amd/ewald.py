@@ -31,6 +31,7 @@ FLAG_VALU_SK = 2
 FLAG_NO_GRAPH = 4
 FLAG_NO_WORKSPACE = 8
 FLAG_ONE_STREAM = 16
+SERVER_FLAG_EXPRESS_CUS = 1
 SCRATCH_BYTES = 64 << 20  # EWALD_SCRATCH_BYTES
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
@@ -56,7 +57,9 @@ class ServerParams(ctypes.Structure):
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("systems", ctypes.c_int64), ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
-                ("in_flight", ctypes.c_int64), ("budget", ctypes.c_uint64), ("used", ctypes.c_uint64)]
+                ("in_flight", ctypes.c_int64), ("budget", ctypes.c_uint64), ("used", ctypes.c_uint64),
+                ("peak_used", ctypes.c_uint64), ("held", ctypes.c_int64), ("held_total", ctypes.c_int64),
+                ("masked_streams", ctypes.c_int64)]
 
 
 class DebugStats(ctypes.Structure):
@@ -106,6 +109,10 @@ def _load():
     lib.ewald_plan_set_stream.argtypes = [vp, vp]
     lib.ewald_energy_forces.restype = ctypes.c_int
     lib.ewald_energy_forces.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    lib.ewald_eval_workspace_bytes.restype = ctypes.c_size_t
+    lib.ewald_eval_workspace_bytes.argtypes = [vp, ctypes.c_int64]
+    lib.ewald_energy_forces_ws.restype = ctypes.c_int
+    lib.ewald_energy_forces_ws.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
     lib.ewald_energy_forces_noalloc.restype = ctypes.c_int
     lib.ewald_energy_forces_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
     lib.ewald_energy.restype = ctypes.c_int
@@ -245,6 +252,24 @@ class Plan:
                                      g.data_ptr() if g is not None else None)
         if st != OK:
             raise EwaldError(st, "ewald_energy_forces")
+        return e, f, g
+
+    def eval_workspace_bytes(self, n: int) -> int:
+        """Bytes of the per-evaluation buffers of an evaluation of ``n`` particles."""
+        return int(_load().ewald_eval_workspace_bytes(self.handle, int(n)))
+
+    def energy_forces_ws(self, pos, q, workspace, out):
+        """Evaluation with the per-evaluation buffers in ``workspace`` (a device
+        tensor of at least ``eval_workspace_bytes(n)`` bytes, 256-byte aligned);
+        ``out`` = (energy[5], forces (n,3) or None, dEdq (n,) or None)."""
+        n = self._check_inputs(pos, q)
+        e, f, g = out
+        nbytes = workspace.numel() * workspace.element_size()
+        st = _load().ewald_energy_forces_ws(self.handle, n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
+                                            f.data_ptr() if f is not None else None,
+                                            g.data_ptr() if g is not None else None, workspace.data_ptr(), nbytes)
+        if st != OK:
+            raise EwaldError(st, "ewald_energy_forces_ws")
         return e, f, g
 
     def energy_forces_noalloc(self, pos, q, out):
@@ -415,11 +440,13 @@ class Server:
     the binding keeps the tensors of a request alive until it is waited for.
     """
 
-    def __init__(self, n_streams: int = 4, precision="mixed", device: int = 0, hbm_budget: int = 0):
+    def __init__(self, n_streams: int = 4, precision="mixed", device: int = 0, hbm_budget: int = 0,
+                 express_cus: bool = False):
         lib = _load()
         import torch
         self.device = torch.device("cuda", device)
-        prm = ServerParams(int(device), int(n_streams), _precision_code(precision), 0, int(hbm_budget))
+        prm = ServerParams(int(device), int(n_streams), _precision_code(precision),
+                           SERVER_FLAG_EXPRESS_CUS if express_cus else 0, int(hbm_budget))
         h = ctypes.c_void_p()
         st = lib.ewald_server_create(ctypes.byref(prm), ctypes.byref(h))
         if st != OK:
