@@ -20,8 +20,8 @@
 //              wave-uniform, so exp(i a theta_z) for the segment is read through the
 //              scalar path, while q exp(i n_x theta_x) exp(i n_y theta_y) per lane comes
 //              from LDS tiles.  Each (particle, slot) costs four FMAs that serve both
-//              +a and -a (the phases are conjugates).  FP32 partials over at most
-//              tile/kSkWaves particles are folded into FP64 (mixed precision).
+//              +a and -a (the phases are conjugates).  Phases, products and sums
+//              are FP64 in both precisions.
 //  * k_sk_reduce sums the chunk partials in a fixed order, forms E_recip partials,
 //              S_k (kept for inspection) and the per-slot gather coefficients.
 //  * k_gather  lanes own particles; the loop over (segment, row) items is uniform so

@@ -83,7 +83,7 @@ def test_workspace_bytes_scale_with_capacity():
     big = ew.workspace_bytes(ew.make_params(100000, 8.0, 0.9, 4.0, 8))
     mixed = ew.workspace_bytes(ew.make_params(100000, 8.0, 0.9, 4.0, 8, precision="mixed"))
     assert 0 < small < big
-    assert mixed < big  # FP32 phase tables
+    assert mixed < big  # FP32 gather coefficients
 
 
 @pytest.mark.parametrize("K", [1, 2, 8, 13, 20, 40])
