@@ -150,7 +150,7 @@ constexpr int kSmTileRows = 16;
 constexpr int kSmNap = 24;
 constexpr int kSmNapSmall = 12;  // the instance for KP <= 2 kSmNapSmall
 constexpr int kSmMaxKP = 2 * kSmNap;  // k_max + 1 <= KP <= kSmMaxKP
-constexpr int kSmStage = 9;  // staged entries per thread, a multiple of 3: 3 P KP <= kSmStage * kSmWaves * kLanes
+constexpr int kSmStage = 9;  // staged entries per thread and buffer, a multiple of 3: 3 P KP <= kSmStage * kSmWaves * kLanes
 int sk_mfma_particles(int KP);
 size_t sk_mfma_smem_bytes(int KP);
 inline int sk_mfma_row_blocks(int n_rows) { return (n_rows + kSmWaves * kSmTileRows - 1) / (kSmWaves * kSmTileRows); }

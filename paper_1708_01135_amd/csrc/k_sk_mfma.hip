@@ -16,7 +16,8 @@
 // and w + 4) pair a heavy tile with a light one and every block gets a similar
 // mix: the waves of a block meet at a barrier after every staged sub-chunk, so
 // a block runs at the pace of its busiest SIMD.  The block stages the q x^n,
-// y^n and z^n tables of P particles at a time in LDS (sk_mfma_particles).  The
+// y^n and z^n tables of P particles at a time in LDS (sk_mfma_particles),
+// loading the next sub-chunk into a second buffer while it multiplies.  The
 // partial sums of the chunk are written in the slot layout of the vector
 // kernel (unit = (64-row group, a segment), a mod 8, row mod 64), so the same
 // fixed-order reduction follows.
@@ -25,6 +26,13 @@
 namespace ewk {
 
 namespace {
+
+// Word 3 of a raw buffer resource on GFX9-family parts (32-bit data format,
+// no swizzle); out-of-range loads return zero.
+constexpr int kBufferWord3 = 0x00020000;
+// s_waitcnt immediate with vmcnt = 0 and expcnt / lgkmcnt left at their
+// maxima (GFX9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int kWaitVmcnt0 = 0x0F70;
 
 // One staged sub-chunk against the wave's tile, on the FP64 4x4x4 instruction
 // (four independent 4x4x4 products per instruction, block g = (l / 4) % 4): a
@@ -89,8 +97,7 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int 
                                                               const int *__restrict__ tile_of, int n_slots,
                                                               d4 *__restrict__ part)
 {
-    extern __shared__ __align__(16) unsigned char smem[];
-    c64 *st = reinterpret_cast<c64 *>(smem);  // [3][P][KP]: q x^n, y^n, z^n
+    extern __shared__ __align__(16) unsigned char smem[];  // two buffers of [3][P][KP]: q x^n, y^n, z^n
     const int nb = n_rblocks * n_chunks;
     const int bid = xcd_remap(blockIdx.x, nb);
     if (bid >= nb) return;  // padding block (uniform over the block)
@@ -117,67 +124,48 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int 
 #pragma unroll
     for (int b = 0; b < NMAX; ++b) are[b] = aim[b] = 0.0;
 
-    // Staging: the three tables of a sub-chunk are each P KP contiguous
-    // entries; thread t stages entries t, t + 512, ... of each (at most
-    // kSmStage / 3).  A whole sub-chunk (all but a chunk's last) needs no
-    // clamping or zero fill.  Entry slots past P KP read entry 0 and are not
-    // stored.
+    // Staging, double-buffered: the three tables of a sub-chunk are each
+    // per = P KP contiguous entries.  While the waves multiply sub-chunk i out
+    // of one LDS buffer, the loads of sub-chunk i + 1 go straight from global
+    // memory into the other (16-byte buffer loads to LDS: a wave's instruction
+    // fills 64 consecutive entries, wave w taking entries 64 w + 512 k), with no
+    // register round trip and no LDS store instructions.  Each table's buffer
+    // resource ends at the sub-chunk's last particle, so the entries of a
+    // partial sub-chunk (a chunk's last) past it load as zero.  The wait on the
+    // wave's own loads (vmcnt) and the barrier at the top of each step make the
+    // buffer complete before any wave reads it; the buffer the next loads
+    // overwrite was last read before that barrier.
     constexpr int kStride = kSmWaves * kLanes;
     constexpr int kPer = kSmStage / 3;
     const int per = P * KP;
+    c64 *const st = reinterpret_cast<c64 *>(smem);  // buffer b at st + 3 per b
     const c64 *tab[3] = {tx, ty, tz};
-    int eidx[kPer];
-    bool euse[kPer];
+    const int wave_e0 = __builtin_amdgcn_readfirstlane(w * kLanes);
+    auto stage = [&](int64_t j0, c64 *dst) {
+        const int64_t left = j_hi - j0;
+        const int valid = (left < P ? (int)left : P) * KP;  // entries of each table
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-        const int e = (int)threadIdx.x + k * kStride;
-        euse[k] = e < per;
-        eidx[k] = euse[k] ? e : 0;
-    }
-    c64 v[3][kPer];
-    auto valid_of = [&](int64_t j0) { return (int)((j_hi - j0 < P ? j_hi - j0 : P) * KP); };
-    auto load_stage = [&](int64_t j0) {
-        const int valid = valid_of(j0);
-        const int64_t o = j0 * KP;
-        if (valid == per) {  // wave-uniform
+        for (int t = 0; t < 3; ++t) {
+            const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<c64 *>(tab[t] + j0 * KP), 0, valid * (int)sizeof(c64), kBufferWord3);
 #pragma unroll
-            for (int t = 0; t < 3; ++t)
-#pragma unroll
-                for (int k = 0; k < kPer; ++k) v[t][k] = tab[t][o + eidx[k]];
-        } else {
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-#pragma unroll
-                for (int k = 0; k < kPer; ++k) v[t][k] = tab[t][o + (eidx[k] < valid ? eidx[k] : 0)];
+            for (int k = 0; k < kPer; ++k) {
+                const int e0 = wave_e0 + k * kStride;
+                if (e0 < per && e0 + lane < per)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                        rs, (__attribute__((address_space(3))) void *)(dst + t * per + e0), 16,
+                        (e0 + lane) * (int)sizeof(c64), 0, 0, 0);
+            }
         }
     };
-    if (j_lo < j_hi) load_stage(j_lo);
+    int cur = 0;
+    if (j_lo < j_hi) stage(j_lo, st);
     for (int64_t j0 = j_lo; j0 < j_hi; j0 += P) {
+        __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
         __syncthreads();
-        const int valid = valid_of(j0);
-        if (valid == per) {  // wave-uniform
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-#pragma unroll
-                for (int k = 0; k < kPer; ++k)
-                    if (euse[k]) st[t * per + eidx[k]] = v[t][k];
-        } else {
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-#pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    if (euse[k]) {
-                        const bool ok = eidx[k] < valid;
-                        c64 w;
-                        w.re = ok ? v[t][k].re : 0.0;
-                        w.im = ok ? v[t][k].im : 0.0;
-                        st[t * per + eidx[k]] = w;
-                    }
-                }
-        }
-        __syncthreads();
-        if (j0 + P < j_hi) load_stage(j0 + P);
-        sk_tile_dispatch<NMAX>(nap, st, per, KP, P, nx, ay, ysg, kq, zc, are, aim);
+        if (j0 + P < j_hi) stage(j0 + P, st + (cur ^ 1) * 3 * per);
+        sk_tile_dispatch<NMAX>(nap, st + cur * 3 * per, per, KP, P, nx, ay, ysg, kq, zc, are, aim);
+        cur ^= 1;
     }
 
     // lane l: row 4 ((l / 4) % 4) + l / 16 of the tile, a = 2b + (l % 4) / 2,
@@ -204,18 +192,31 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int 
 
 }  // namespace
 
-// Particles per staged sub-chunk: the largest of 48, 32, 16, 8 (a multiple of
-// 8, two quads per step) whose three tables (3 P KP entries) fit kSmStage
-// entries per thread.  0 if even 8 do not fit.
+// Particles per staged sub-chunk (a multiple of 8: two quads per step).  The
+// two buffers take 2 x 3 P KP entries of LDS, and the structure factor runs
+// beside the real-space kernels, whose blocks need LDS on the same compute
+// units: P is the largest of 48, 40, 32, 24, 16, 8 whose two buffers stay
+// within 2 x 1792 entries (56 KiB), as long as that P is at least 24;
+// otherwise (large k_max) the largest P <= 32 whose tables fit kSmStage
+// entries per thread, so that a step still holds enough quads to cover its
+// barrier.  Measured: rock salt 32^3 (k_max 20) took 0.203 ms per evaluation
+// with P = 24 and 0.211 with P = 48; rock salt 64^3 (k_max 32) 3.74 ms with
+// P = 32 and 4.18 with P = 8.  0 if even 8 particles do not fit.
 int sk_mfma_particles(int KP)
 {
-    static const int kCand[4] = {48, 32, 16, 8};
-    for (int c = 0; c < 4; ++c)
+    static const int kCand[6] = {48, 40, 32, 24, 16, 8};
+    constexpr int kSmallStage = 1792;
+    for (int c = 0; c < 6; ++c)
+        if (3 * kCand[c] * KP <= kSmallStage) {
+            if (kCand[c] >= 24) return kCand[c];
+            break;
+        }
+    for (int c = 2; c < 6; ++c)
         if (3 * kCand[c] * KP <= kSmStage * kSmWaves * kLanes) return kCand[c];
     return 0;
 }
 
-size_t sk_mfma_smem_bytes(int KP) { return (size_t)3 * sk_mfma_particles(KP) * KP * sizeof(c64); }
+size_t sk_mfma_smem_bytes(int KP) { return (size_t)2 * 3 * sk_mfma_particles(KP) * KP * sizeof(c64); }
 
 hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx,
                           const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny, const int *row_m,
