@@ -164,7 +164,10 @@ constexpr int mfma_block_particles()
 {
     return sizeof(R) == 4 ? 32 : 32;
 }
-size_t gather_mfma_smem_bytes(int nap_max, bool fp64);
+// LDS of the z-power stage alone, and of the whole matrix-core gather block
+// (stage and phase tables, or the cross-wave sums if larger).
+size_t gather_mfma_stage_bytes(int nap_max, bool fp64);
+size_t gather_mfma_smem_bytes(int nap_max, int K, bool fp64);
 template <typename R>
 hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, int nap_max,
                               const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart);

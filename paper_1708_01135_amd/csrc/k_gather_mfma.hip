@@ -15,9 +15,14 @@
 // (tile, a pair); the z powers of the block's particles are staged once in
 // LDS.  Lane l owns particle l % 16 of each sub-tile and, in output register
 // r, row 4 (l / 16) + r (FP32) or 4 r + l / 16 (FP64); the plan places quad
-// l / 16's n_y offset r there, so the lane's phases P follow from one FP64
-// sincos and a recurrence along n_y.  Sums over rows are FP64 per lane, then
-// reduced over the four lane groups and the block's waves in a fixed order.
+// l / 16's n_y offset r there.  The phase P of the quad's first row comes from
+// one reduced FP64 argument and FP32 polynomials (FP32), or (FP64) from x^n
+// and y^n tables (0 <= n <= k_max) that the block builds in LDS for its
+// particles (FP64 recurrences from one sincos per eight powers): one complex
+// product instead of a library sincos per quad and particle.  The other three
+// rows follow by a recurrence along n_y.  Sums over rows are FP64 per lane,
+// then reduced over the four lane groups and the block's waves in a fixed
+// order.
 //
 // FP32 (MIXED): FP32 operands and MFMA accumulation over a, FP32 phases P,
 // FP64 sums over rows.  FP64: every step in double (FP64 MFMA).
@@ -81,6 +86,20 @@ __device__ inline void row_phase<float>(double th, float &c, float &s)
 }
 
 template <typename R>
+struct RC {
+    R re, im;
+};
+
+// The FP64 gather takes its phases from LDS tables (a library FP64 sincos per
+// quad and particle cost more than building them); the FP32 one from
+// row_phase (measured: tables made it slower at rock salt 32^3).
+template <typename R>
+constexpr bool gather_tables()
+{
+    return sizeof(R) == 8;
+}
+
+template <typename R>
 constexpr int zs_stride()
 {
     // padded LDS stride of one k component: the four 16-lane groups of a read
@@ -89,7 +108,7 @@ constexpr int zs_stride()
 }
 
 template <typename R>
-__global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int nap_max,
+__global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int K, int nap_max,
                                                                   SplitTable split, const d4 *__restrict__ pq,
                                                                   const c64 *__restrict__ tz,
                                                                   const MTile *__restrict__ tiles,
@@ -134,23 +153,62 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     }
 
     const double gk = 2.0 * kPi / L;
+    constexpr bool kTab = gather_tables<R>();
+    // FP64: x^n and y^n (n <= K) of the block's particles, entry (axis, n, col)
+    // at ptab[(axis (K + 1) + n) NP + col].  Thread task (axis, block of eight
+    // powers, col): one sincos at the block's first power and one for the
+    // step, then the recurrence.
+    const int K1 = K + 1;
+    RC<R> *ptab = reinterpret_cast<RC<R> *>(zs + (size_t)nap_max * 4 * ZS);
+    if constexpr (kTab) {
+        const int nb8 = (K1 + 7) / 8;
+        for (int idx = (int)threadIdx.x; idx < 2 * nb8 * NP; idx += kGmWaves * kLanes) {
+            const int col = idx % NP, b = (idx / NP) % nb8, axis = idx / (NP * nb8);
+            int64_t j = p0 + col;
+            j = j < n ? j : n - 1;
+            const d4 r = pq[j];
+            const double th = gk * (axis ? r.b : r.a);
+            double s0, c0, s1, c1;
+            sincos((double)(8 * b) * th, &s0, &c0);
+            sincos(th, &s1, &c1);
+            RC<R> *o = ptab + ((size_t)axis * K1 + 8 * b) * NP + col;
+            const int cnt = K1 - 8 * b < 8 ? K1 - 8 * b : 8;
+            for (int m = 0; m < cnt; ++m) {
+                o[(size_t)m * NP] = RC<R>{(R)c0, (R)s0};
+                const double t = c0 * c1 - s0 * s1;
+                s0 = c0 * s1 + s0 * c1;
+                c0 = t;
+            }
+        }
+    }
     double thx[NSUB], thy[NSUB];
     R cy[NSUB], sy[NSUB];
     double ph[NSUB], fx[NSUB], fy[NSUB], fz[NSUB];
 #pragma unroll
     for (int s = 0; s < NSUB; ++s) {
-        int64_t j = p0 + 16 * s + (lane & 15);
-        j = j < n ? j : n - 1;
-        const d4 r = pq[j];
-        thx[s] = gk * r.a;
-        thy[s] = gk * r.b;
-        double sn, cs;
-        sincos(thy[s], &sn, &cs);
-        cy[s] = (R)cs;
-        sy[s] = (R)sn;
         ph[s] = fx[s] = fy[s] = fz[s] = 0.0;
+        if constexpr (!kTab) {
+            int64_t j = p0 + 16 * s + (lane & 15);
+            j = j < n ? j : n - 1;
+            const d4 r = pq[j];
+            thx[s] = gk * r.a;
+            thy[s] = gk * r.b;
+            double sn, cs;
+            sincos(thy[s], &sn, &cs);
+            cy[s] = (R)cs;
+            sy[s] = (R)sn;
+        }
     }
     __syncthreads();
+    if constexpr (kTab) {
+        // the n_y step of the row recurrence: y^1 of the lane's particles
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            const RC<R> y1 = ptab[((size_t)K1 + (K1 > 1 ? 1 : 0)) * NP + 16 * s + (lane & 15)];
+            cy[s] = y1.re;
+            sy[s] = y1.im;
+        }
+    }
 
     const int g = lane >> 4;  // quad of this lane
     const int lo = split.lo[blockIdx.y], hi = split.lo[blockIdx.y + 1];
@@ -221,7 +279,16 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
 #pragma unroll
         for (int s = 0; s < NSUB; ++s) {
             R pr, pi;
-            row_phase<R>((double)nx * thx[s] + (double)ny0 * thy[s], pr, pi);
+            if constexpr (kTab) {  // P = x^nx y^ny0, y^-a = conj y^a
+                const int ay = ny0 < 0 ? -ny0 : ny0;
+                const RC<R> xv = ptab[(size_t)nx * NP + 16 * s + (lane & 15)];
+                const RC<R> yv = ptab[((size_t)K1 + ay) * NP + 16 * s + (lane & 15)];
+                const R yi = ny0 < 0 ? -yv.im : yv.im;
+                pr = xv.re * yv.re - xv.im * yi;
+                pi = xv.re * yi + xv.im * yv.re;
+            } else {
+                row_phase<R>((double)nx * thx[s] + (double)ny0 * thy[s], pr, pi);
+            }
             R sre = 0, sim = 0, srim = 0, simz = 0;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -289,10 +356,21 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
 
 }  // namespace
 
-size_t gather_mfma_smem_bytes(int nap_max, bool fp64)
+size_t gather_mfma_stage_bytes(int nap_max, bool fp64)
 {
-    const size_t stage = fp64 ? (size_t)nap_max * 4 * zs_stride<double>() * sizeof(double)
-                              : (size_t)nap_max * 4 * zs_stride<float>() * sizeof(float);
+    return fp64 ? (size_t)nap_max * 4 * zs_stride<double>() * sizeof(double)
+                : (size_t)nap_max * 4 * zs_stride<float>() * sizeof(float);
+}
+
+size_t gather_mfma_smem_bytes(int nap_max, int K, bool fp64)
+{
+    const size_t tab = fp64 ? (gather_tables<double>() ? (size_t)2 * (K + 1) * mfma_block_particles<double>() *
+                                                             sizeof(RC<double>)
+                                                       : 0)
+                            : (gather_tables<float>() ? (size_t)2 * (K + 1) * mfma_block_particles<float>() *
+                                                            sizeof(RC<float>)
+                                                      : 0);
+    const size_t stage = gather_mfma_stage_bytes(nap_max, fp64) + tab;
     const size_t red = (size_t)kGmWaves * (fp64 ? mfma_block_particles<double>() : mfma_block_particles<float>()) *
                        sizeof(d4);
     return stage > red ? stage : red;
@@ -303,8 +381,8 @@ hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, co
                               const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart)
 {
     const int blocks = ceil_div(a.n, mfma_block_particles<R>());
-    const size_t smem = gather_mfma_smem_bytes(nap_max, sizeof(R) == 8);
-    hipLaunchKernelGGL(k_gather_mfma<R>, dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L, a.KP,
+    const size_t smem = gather_mfma_smem_bytes(nap_max, a.K, sizeof(R) == 8);
+    hipLaunchKernelGGL(k_gather_mfma<R>, dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L, a.KP, a.K,
                        nap_max, split, pq, tz, tiles, mcoef, gpart);
     return hipGetLastError();
 }

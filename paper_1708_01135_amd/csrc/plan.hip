@@ -706,8 +706,9 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmMaxKP &&
                  sk_mfma_particles(p->kl.KP) >= 8;
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
+    // (its x^n, y^n tables come on top: at most 86 KB at k_max 83 in FP64)
     p->mfma_gather = !(params->flags & EWALD_FLAG_VALU_GATHER) &&
-                     gather_mfma_smem_bytes(p->kl.nap_max, !p->mixed) <= 64 * 1024;
+                     gather_mfma_stage_bytes(p->kl.nap_max, !p->mixed) <= 64 * 1024;
 
     // C_k by integer |n|^2 (computed once on the host in FP64)
     const int K = params->k_max;
