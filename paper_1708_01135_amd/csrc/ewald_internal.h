@@ -87,7 +87,7 @@ hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill,
                        int *item_off, int *n_items);
 hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, const int *cell_start,
                           int *fill, int *tmp_idx);
-hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, const int *tmp_idx,
+hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, int *tmp_idx,
                            const double *pos, const double *q, int *perm, d4 *pq);
 
 struct RecipArgs {

@@ -1,5 +1,5 @@
 // Cell list for the real-space pair loop: positions are reduced into [0, L)^3,
-// binned into nc^3 cubic cells of side h = L / nc >= r_c, and copied into
+// binned into nc^3 cubic cells of side h = L / nc >= r_c / 2, and copied into
 // cell-sorted 32-byte records (x, y, z, q).  Inside a cell particles keep their
 // input order, so every later floating-point sum runs in a fixed order and
 // results are bitwise reproducible.
@@ -11,7 +11,8 @@
 //   scan     : exclusive scan of the counts (tile totals, then one block per
 //              tile), pair-loop work items, total charge;
 //   scatter  : slot claim inside each cell (order not yet deterministic);
-//   cellsort : per cell, rank by input index and write the sorted records.
+//   cellsort : per cell, restore input order (rank, or sort the indices) and
+//              write the sorted records.
 #include <algorithm>
 
 #include "ewald_internal.h"
@@ -239,13 +240,55 @@ __global__ __launch_bounds__(256) void k_scatter(int64_t n, const int *__restric
 
 constexpr int kSortThreads = 128;
 constexpr int kSortLds = 2048;
+constexpr int kSortRank = 256;  // cells up to this size are ranked directly
+
+// Ascending bitonic sort of v[0, cnt) by one workgroup, in the variant whose
+// every compare-exchange puts the smaller value at the lower index (the first
+// step of each merge compares mirrored positions of a block, the later steps
+// positions j apart).  Positions past cnt stand for +infinity, so a pair whose
+// upper position is past cnt never exchanges and is skipped: no padding is
+// stored.  O(cnt log^2 cnt) work, (log2 P)(log2 P + 1) / 2 barriers for P the
+// power of two at or above cnt.  V is a pointer to LDS or to global memory
+// (the workgroup barrier orders both).
+template <typename V>
+__device__ inline void bitonic_sort_block(V v, int cnt)
+{
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = (int)threadIdx.x; t < P / 2; t += kSortThreads) {
+                const int blk = t / j, o = t % j;
+                int lo, hi;
+                if (j == k >> 1) {  // mirrored positions of a block of k
+                    lo = blk * k + o;
+                    hi = blk * k + k - 1 - o;
+                } else {
+                    lo = blk * 2 * j + o;
+                    hi = lo + j;
+                }
+                if (hi < cnt) {
+                    const int x = v[lo], y = v[hi];
+                    if (y < x) {
+                        v[lo] = y;
+                        v[hi] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
 
 // One workgroup per cell.  The scatter above claimed slots in arbitrary order;
-// the rank of an entry is the number of entries of the same cell with a smaller
-// input index, so writing to cell_start + rank restores input order.
+// the cell's entries go back to input order: an entry's rank is the number of
+// entries of the cell with a smaller input index (cells of at most kSortRank
+// entries), or the cell's indices are sorted (bitonic, in LDS up to kSortLds
+// entries, in place in tmp_idx beyond), so that the rank is the position.
+// Either way the order is the same, and O(cnt log^2 cnt) bounds the work of
+// a crowded cell.
 __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *__restrict__ cell_start,
-                                                           const int *__restrict__ tmp_idx,
-                                                           const double *__restrict__ pos,
+                                                           int *__restrict__ tmp_idx, const double *__restrict__ pos,
                                                            const double *__restrict__ q, int *__restrict__ perm,
                                                            d4 *__restrict__ pq)
 {
@@ -253,18 +296,24 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
     const int c = blockIdx.x;
     const int start = cell_start[c];
     const int cnt = cell_start[c + 1] - start;
-    const bool in_lds = cnt <= kSortLds;
+    const bool in_lds = cnt <= kSortLds;  // uniform over the workgroup
+    const bool ranked = cnt <= kSortRank;
     if (in_lds) {
         for (int e = threadIdx.x; e < cnt; e += kSortThreads) s_idx[e] = tmp_idx[start + e];
     }
     __syncthreads();
+    if (!ranked) {
+        if (in_lds)
+            bitonic_sort_block(s_idx, cnt);
+        else
+            bitonic_sort_block(tmp_idx + start, cnt);
+    }
     for (int e = threadIdx.x; e < cnt; e += kSortThreads) {
         const int mine = in_lds ? s_idx[e] : tmp_idx[start + e];
-        int rank = 0;
-        if (in_lds) {
+        int rank = e;
+        if (ranked) {
+            rank = 0;
             for (int f = 0; f < cnt; ++f) rank += s_idx[f] < mine;
-        } else {
-            for (int f = 0; f < cnt; ++f) rank += tmp_idx[start + f] < mine;
         }
         const int s = start + rank;
         perm[s] = mine;
@@ -328,7 +377,7 @@ hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, 
     return hipGetLastError();
 }
 
-hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, const int *tmp_idx,
+hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, int *tmp_idx,
                            const double *pos, const double *q, int *perm, d4 *pq)
 {
     hipLaunchKernelGGL(k_cellsort, dim3(a.ncell), dim3(kSortThreads), 0, s, a.L, cell_start, tmp_idx, pos, q,

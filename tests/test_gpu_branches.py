@@ -113,3 +113,18 @@ def test_dense_cluster_fallbacks(precision):
     compare(got, oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST), precision, "cluster")
     assert stats["max_cell_count"] > 2048
     assert stats["direct_particles"] >= 3000
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+def test_crowded_cell_sorted_in_lds(precision):
+    # 1200 ions in a 1.2^3 cube inside one cell: between the directly ranked
+    # cell sizes and the global-memory sort, the cell's indices are sorted in
+    # LDS; the order (and so every sum) must not depend on the scatter's races
+    L, a, rc, K = 14.0, 1.0, 3.5, 10
+    pos, q = wl.clustered(1200, 2000, L, (0.3, 0.3, 0.3), 1.2, seed=12)
+    got, stats = run_with_stats(pos, q, L, a, rc, K, precision)
+    compare(got, oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST), precision, "crowded cell")
+    assert 256 < stats["max_cell_count"] <= 2048
+    again, _ = run_with_stats(pos, q, L, a, rc, K, precision)
+    for x, y in zip(got, again):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
