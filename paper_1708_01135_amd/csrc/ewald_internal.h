@@ -158,16 +158,19 @@ inline int sk_mfma_row_blocks(int n_rows) { return (n_rows + kSmWaves * kSmTileR
 hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx,
                           const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny, const int *row_m,
                           const int *unit_base, const int *tile_of, d4 *part);
-// particles per block of the matrix-core gather (16 per sub-tile)
-template <typename R>
-constexpr int mfma_block_particles()
-{
-    return sizeof(R) == 4 ? 32 : 32;
-}
+// Particles per block of the matrix-core gather (16 per sub-tile): 32, or in
+// FP32 64 from 65536 particles on.  A block streams every coefficient of its
+// row split once, so 64 halves that traffic; below 65536 particles the
+// 32-particle blocks' higher occupancy wins (measured: rock salt 32^3 took
+// 0.225 ms per evaluation with 64 against 0.210 with 32; 64^3 3.70 against
+// 3.75-3.80 ms).
+constexpr int64_t kGatherWideFrom = 65536;
+inline int gather_mfma_particles(int64_t n, bool fp64) { return !fp64 && n >= kGatherWideFrom ? 64 : 32; }
 // LDS of the z-power stage alone, and of the whole matrix-core gather block
-// (stage and phase tables, or the cross-wave sums if larger).
-size_t gather_mfma_stage_bytes(int nap_max, bool fp64);
-size_t gather_mfma_smem_bytes(int nap_max, int K, bool fp64);
+// (stage and phase tables, or the cross-wave sums if larger), for blocks of np
+// particles.
+size_t gather_mfma_stage_bytes(int nap_max, int np, bool fp64);
+size_t gather_mfma_smem_bytes(int nap_max, int np, int K, bool fp64);
 template <typename R>
 hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, int nap_max,
                               const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart);

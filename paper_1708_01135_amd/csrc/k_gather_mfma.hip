@@ -99,15 +99,11 @@ constexpr bool gather_tables()
     return sizeof(R) == 8;
 }
 
-template <typename R>
-constexpr int zs_stride()
-{
-    // padded LDS stride of one k component: the four 16-lane groups of a read
-    // start 16 (FP32) or 32 (FP64) banks apart
-    return mfma_block_particles<R>() + 16;
-}
+// padded LDS stride of one k component for blocks of NP particles: the four
+// 16-lane groups of a read start 16 (FP32) or 32 (FP64) banks apart
+constexpr int zs_stride(int np) { return np + 16; }
 
-template <typename R>
+template <typename R, int NP>
 __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int K, int nap_max,
                                                                   SplitTable split, const d4 *__restrict__ pq,
                                                                   const c64 *__restrict__ tz,
@@ -115,9 +111,8 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
                                                                   const R *__restrict__ coef, d4 *__restrict__ gpart)
 {
     using V = typename Mfma<R>::v4;
-    constexpr int NP = mfma_block_particles<R>();
     constexpr int NSUB = NP / 16;
-    constexpr int ZS = zs_stride<R>();
+    constexpr int ZS = zs_stride(NP);
     extern __shared__ __align__(16) unsigned char smem[];
     R *zs = reinterpret_cast<R *>(smem);  // [nap_max][4][ZS]
 
@@ -356,23 +351,17 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
 
 }  // namespace
 
-size_t gather_mfma_stage_bytes(int nap_max, bool fp64)
+size_t gather_mfma_stage_bytes(int nap_max, int np, bool fp64)
 {
-    return fp64 ? (size_t)nap_max * 4 * zs_stride<double>() * sizeof(double)
-                : (size_t)nap_max * 4 * zs_stride<float>() * sizeof(float);
+    return (size_t)nap_max * 4 * zs_stride(np) * (fp64 ? sizeof(double) : sizeof(float));
 }
 
-size_t gather_mfma_smem_bytes(int nap_max, int K, bool fp64)
+size_t gather_mfma_smem_bytes(int nap_max, int np, int K, bool fp64)
 {
-    const size_t tab = fp64 ? (gather_tables<double>() ? (size_t)2 * (K + 1) * mfma_block_particles<double>() *
-                                                             sizeof(RC<double>)
-                                                       : 0)
-                            : (gather_tables<float>() ? (size_t)2 * (K + 1) * mfma_block_particles<float>() *
-                                                            sizeof(RC<float>)
-                                                      : 0);
-    const size_t stage = gather_mfma_stage_bytes(nap_max, fp64) + tab;
-    const size_t red = (size_t)kGmWaves * (fp64 ? mfma_block_particles<double>() : mfma_block_particles<float>()) *
-                       sizeof(d4);
+    const bool tables = fp64 ? gather_tables<double>() : gather_tables<float>();
+    const size_t tab = tables ? (size_t)2 * (K + 1) * np * (fp64 ? sizeof(RC<double>) : sizeof(RC<float>)) : 0;
+    const size_t stage = gather_mfma_stage_bytes(nap_max, np, fp64) + tab;
+    const size_t red = (size_t)kGmWaves * np * sizeof(d4);
     return stage > red ? stage : red;
 }
 
@@ -380,10 +369,16 @@ template <typename R>
 hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, int nap_max,
                               const d4 *pq, const c64 *tz, const MTile *tiles, const R *mcoef, d4 *gpart)
 {
-    const int blocks = ceil_div(a.n, mfma_block_particles<R>());
-    const size_t smem = gather_mfma_smem_bytes(nap_max, a.K, sizeof(R) == 8);
-    hipLaunchKernelGGL(k_gather_mfma<R>, dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L, a.KP, a.K,
-                       nap_max, split, pq, tz, tiles, mcoef, gpart);
+    const bool fp64 = sizeof(R) == 8;
+    const int np = gather_mfma_particles(a.n, fp64);
+    const int blocks = ceil_div(a.n, np);
+    const size_t smem = gather_mfma_smem_bytes(nap_max, np, a.K, fp64);
+    if (np == 64)
+        hipLaunchKernelGGL((k_gather_mfma<R, 64>), dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L,
+                           a.KP, a.K, nap_max, split, pq, tz, tiles, mcoef, gpart);
+    else
+        hipLaunchKernelGGL((k_gather_mfma<R, 32>), dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L,
+                           a.KP, a.K, nap_max, split, pq, tz, tiles, mcoef, gpart);
     return hipGetLastError();
 }
 

@@ -237,7 +237,7 @@ int sk_mfma_chunk_cap(const KLayout &kl)
 
 int gather_mfma_split(int64_t n, const KLayout &kl, bool fp64)
 {
-    const int np = fp64 ? mfma_block_particles<double>() : mfma_block_particles<float>();
+    const int np = gather_mfma_particles(n, fp64);
     const int64_t blocks = (n + np - 1) / np;
     int64_t s = (kMfmaTargetBlocks + blocks - 1) / blocks;
     s = std::min<int64_t>(s, (int64_t)kl.mtiles.size() / 8);
@@ -708,7 +708,8 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
     // (its x^n, y^n tables come on top: at most 86 KB at k_max 83 in FP64)
     p->mfma_gather = !(params->flags & EWALD_FLAG_VALU_GATHER) &&
-                     gather_mfma_stage_bytes(p->kl.nap_max, !p->mixed) <= 64 * 1024;
+                     gather_mfma_stage_bytes(p->kl.nap_max, gather_mfma_particles(params->n_max, !p->mixed),
+                                             !p->mixed) <= 64 * 1024;
 
     // C_k by integer |n|^2 (computed once on the host in FP64)
     const int K = params->k_max;
@@ -1218,11 +1219,12 @@ ewald_status ewald_debug_stats_read(ewald_plan_t p, int64_t n, ewald_debug_stats
         out->sk_mfma_flops = subchunks * (P / 4) * 2 * naps * 512;
     }
     if (p->mfma_gather) {
-        // every block of 32 particles: 4 quantities x 2 sub-tiles of 16 per pair of a of every tile
+        // every block of np particles: 4 quantities x np / 16 sub-tiles per pair of a of every tile
         int64_t naps = 0;
         for (const MTile &t : kl.mtiles) naps += t.nap;
-        const int64_t blocks = (n + 31) / 32;
-        out->gather_mfma_flops = blocks * 8 * naps * 2048;
+        const int np = gather_mfma_particles(n, !p->mixed);
+        const int64_t blocks = (n + np - 1) / np;
+        out->gather_mfma_flops = blocks * 4 * (np / 16) * naps * 2048;
     }
     return EWALD_OK;
 }
