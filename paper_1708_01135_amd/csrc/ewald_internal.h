@@ -87,6 +87,15 @@ hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill,
                        int *item_off, int *n_items);
 hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, const int *cell_start,
                           int *fill, int *tmp_idx);
+// One-workgroup cell list of a small system (n <= kSmallCellsMaxN, ncell <=
+// kSmallCellsMaxCells): the outputs of bin, scan, scatter and cellsort, bit
+// for bit (counts, fill and tile sums are not touched).
+constexpr int kSmallCellsMaxN = 2048;
+constexpr int kSmallCellsMaxCells = 4096;
+bool cells_small(const CellArgs &a);
+hipError_t launch_cells_small(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_start,
+                              int *item_cell, int *item_off, int *n_items, double *scalars, int *perm, d4 *pq,
+                              int *status);
 hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, int *tmp_idx,
                            const double *pos, const double *q, int *perm, d4 *pq);
 
@@ -215,6 +224,12 @@ struct FinalArgs {
 hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
                                      const d4 *freal, const d4 *gpart, const double *scalars,
                                      double *forces, double *dEdq, double *epart);
+// Both totals passes in one workgroup for a small system (n <= 2048), with the
+// same sums in the same order as launch_finalize_particles + _energy.
+bool finalize_small(int64_t n);
+hipError_t launch_finalize_small(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm, const d4 *freal,
+                                 const d4 *gpart, const double *scalars, double *forces, double *dEdq,
+                                 const double *erec_part, const int *status, double *energy);
 hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const double *epart, int n_epart,
                                   const double *erec_part, const double *scalars, const int *status,
                                   double *energy);

@@ -13,6 +13,8 @@
 //   scatter  : slot claim inside each cell (order not yet deterministic);
 //   cellsort : per cell, restore input order (rank, or sort the indices) and
 //              write the sorted records.
+// A small system (at most 2048 particles and 4096 cells) takes all four steps
+// in one workgroup (k_cells_small), with the same results.
 #include <algorithm>
 
 #include "ewald_internal.h"
@@ -250,14 +252,14 @@ constexpr int kSortRank = 256;  // cells up to this size are ranked directly
 // stored.  O(cnt log^2 cnt) work, (log2 P)(log2 P + 1) / 2 barriers for P the
 // power of two at or above cnt.  V is a pointer to LDS or to global memory
 // (the workgroup barrier orders both).
-template <typename V>
+template <int THREADS, typename V>
 __device__ inline void bitonic_sort_block(V v, int cnt)
 {
     int P = 1;
     while (P < cnt) P <<= 1;
     for (int k = 2; k <= P; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = (int)threadIdx.x; t < P / 2; t += kSortThreads) {
+            for (int t = (int)threadIdx.x; t < P / 2; t += THREADS) {
                 const int blk = t / j, o = t % j;
                 int lo, hi;
                 if (j == k >> 1) {  // mirrored positions of a block of k
@@ -304,9 +306,9 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
     __syncthreads();
     if (!ranked) {
         if (in_lds)
-            bitonic_sort_block(s_idx, cnt);
+            bitonic_sort_block<kSortThreads>(s_idx, cnt);
         else
-            bitonic_sort_block(tmp_idx + start, cnt);
+            bitonic_sort_block<kSortThreads>(tmp_idx + start, cnt);
     }
     for (int e = threadIdx.x; e < cnt; e += kSortThreads) {
         const int mine = in_lds ? s_idx[e] : tmp_idx[start + e];
@@ -323,6 +325,158 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
         r.c = wrap_coord(pos[3 * (int64_t)mine + 2], L);
         r.d = q[mine];
         pq[s] = r;
+    }
+}
+
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallIndexBits = 11;  // kSmallCellsMaxN = 2^11
+
+// The whole cell list of a small system (n <= kSmallCellsMaxN, ncell <=
+// kSmallCellsMaxCells) in one workgroup, with the outputs of the four kernels
+// above bit for bit: the same cells, charge sums in the same order (trees over
+// 256-particle chunks as k_bin, then the tree of k_scan_tiles), the same
+// cell_start and pair-work items, and particles in cell order, input order
+// inside a cell (a bitonic sort of the keys cell << 11 | index in LDS).  One
+// launch instead of four, which is most of a small system's real-space path.
+__global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, int nc,
+                                                               const double *__restrict__ pos,
+                                                               const double *__restrict__ q,
+                                                               int *__restrict__ cell_start,
+                                                               int *__restrict__ item_cell, int *__restrict__ item_off,
+                                                               int *__restrict__ n_items, double *__restrict__ scalars,
+                                                               int *__restrict__ perm, d4 *__restrict__ pq,
+                                                               int *__restrict__ status)
+{
+    __shared__ int s_key[kSmallCellsMaxN];
+    __shared__ int s_cnt[kSmallCellsMaxCells];
+    __shared__ double s_a[kSmallThreads], s_b[kSmallThreads];
+    __shared__ double s_qp[2 * (kSmallCellsMaxN / kBinThreads)];
+    __shared__ int2 s_w[kSmallThreads / kLanes];
+    const int t = (int)threadIdx.x, lane = t % kLanes, wave = t / kLanes;
+    const int ncell = nc * nc * nc;
+    const int nq = (n + kBinThreads - 1) / kBinThreads;
+    for (int c = t; c < ncell; c += kSmallThreads) s_cnt[c] = 0;
+    __syncthreads();
+    // cells, keys and counts; charge partials of each chunk of kBinThreads
+    for (int base = 0; base < n; base += kSmallThreads) {
+        const int i = base + t;
+        double qi = 0.0;
+        if (i < n) {
+            const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
+            qi = q[i];
+            const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qi);
+            int c = 0;
+            if (fin)
+                c = (cell_coord(wrap_coord(x, L), L, nc) * nc + cell_coord(wrap_coord(y, L), L, nc)) * nc +
+                    cell_coord(wrap_coord(z, L), L, nc);
+            else
+                atomicOr(status, 1);
+            s_key[i] = (c << kSmallIndexBits) | i;
+            atomicAdd(&s_cnt[c], 1);
+        }
+        s_a[t] = qi;
+        s_b[t] = qi * qi;
+        __syncthreads();
+        const int g = t % kBinThreads;
+        for (int w = kBinThreads / 2; w > 0; w >>= 1) {
+            if (g < w) {
+                s_a[t] += s_a[t + w];
+                s_b[t] += s_b[t + w];
+            }
+            __syncthreads();
+        }
+        const int b = (base + t) / kBinThreads;
+        if (g == 0 && b < nq) {
+            s_qp[2 * b] = s_a[t];
+            s_qp[2 * b + 1] = s_b[t];
+        }
+        __syncthreads();
+    }
+    // Q and sum q^2 (k_scan_tiles' last block: chunk k on thread k, then a tree)
+    if (t < kScanThreads) {
+        double a = 0.0, b = 0.0;
+        if (t < nq) {
+            a += s_qp[2 * t];
+            b += s_qp[2 * t + 1];
+        }
+        s_a[t] = a;
+        s_b[t] = b;
+    }
+    __syncthreads();
+    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            s_a[t] += s_a[t + w];
+            s_b[t] += s_b[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        scalars[0] = s_a[0];
+        scalars[1] = s_b[0];
+    }
+    bitonic_sort_block<kSmallThreads>(s_key, n);
+    // exclusive scans of the counts and of the pair-work items, kScanPer cells
+    // per thread (ncell <= kScanPer kSmallThreads)
+    const int c0 = t * kScanPer;
+    int cnt[kScanPer];
+    int la = 0, lb = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        cnt[u] = c0 + u < ncell ? s_cnt[c0 + u] : 0;
+        la += cnt[u];
+        lb += items_of(cnt[u]);
+    }
+    int ia = la, ib = lb;
+#pragma unroll
+    for (int d = 1; d < kLanes; d <<= 1) {
+        const int xa = __shfl_up(ia, d), xb = __shfl_up(ib, d);
+        if (lane >= d) {
+            ia += xa;
+            ib += xb;
+        }
+    }
+    if (lane == kLanes - 1) s_w[wave] = make_int2(ia, ib);
+    __syncthreads();
+    int wa = 0, wb = 0, ta = 0, tb = 0;
+#pragma unroll
+    for (int w = 0; w < kSmallThreads / kLanes; ++w) {
+        const int2 x = s_w[w];
+        if (w < wave) {
+            wa += x.x;
+            wb += x.y;
+        }
+        ta += x.x;
+        tb += x.y;
+    }
+    int run = wa + ia - la;
+    int irun = wb + ib - lb;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+        const int c = c0 + u;
+        if (c < ncell) {
+            cell_start[c] = run;
+            run += cnt[u];
+            for (int o = 0; o < cnt[u]; o += kPairHome) {
+                item_cell[irun] = c;
+                item_off[irun] = o;
+                ++irun;
+            }
+        }
+    }
+    if (t == 0) {
+        cell_start[ncell] = ta;
+        *n_items = tb;
+    }
+    // records in cell order
+    for (int k = t; k < n; k += kSmallThreads) {
+        const int mine = s_key[k] & ((1 << kSmallIndexBits) - 1);
+        perm[k] = mine;
+        d4 r;
+        r.a = wrap_coord(pos[3 * (int64_t)mine], L);
+        r.b = wrap_coord(pos[3 * (int64_t)mine + 1], L);
+        r.c = wrap_coord(pos[3 * (int64_t)mine + 2], L);
+        r.d = q[mine];
+        pq[k] = r;
     }
 }
 
@@ -386,5 +540,16 @@ hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_sta
 }
 
 int bin_blocks(int64_t n) { return ceil_div(n, kBinThreads); }
+
+bool cells_small(const CellArgs &a) { return a.n <= kSmallCellsMaxN && a.ncell <= kSmallCellsMaxCells; }
+
+hipError_t launch_cells_small(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_start,
+                              int *item_cell, int *item_off, int *n_items, double *scalars, int *perm, d4 *pq,
+                              int *status)
+{
+    hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, (int)a.n, a.L, a.nc, pos, q, cell_start,
+                       item_cell, item_off, n_items, scalars, perm, pq, status);
+    return hipGetLastError();
+}
 
 }  // namespace ewk

@@ -866,13 +866,21 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
     if (!one_stream && e == hipSuccess) e = hipEventRecord(p->ev_join, ax);
 
     // Real space on the caller's stream.
-    run(s, KC_BIN, [&] { return launch_bin(s, ca, pos, q, w.cell_of, w.counts, w.qpart, p->status); });
-    run(s, KC_SCAN, [&] {
-        return launch_scan(s, ca, w.counts, w.fill, w.cell_start, w.qpart, nqb, w.scalars, w.tile_sums,
-                           w.pitem_cell, w.pitem_off, w.n_pitems);
-    });
-    run(s, KC_SCATTER, [&] { return launch_scatter(s, ca, w.cell_of, w.cell_start, w.fill, w.tmp_idx); });
-    run(s, KC_CELLSORT, [&] { return launch_cellsort(s, ca, w.cell_start, w.tmp_idx, pos, q, w.perm, w.pq); });
+    if (cells_small(ca)) {  // one workgroup, same results
+        run(s, KC_BIN, [&] {
+            return launch_cells_small(s, ca, pos, q, w.cell_start, w.pitem_cell, w.pitem_off, w.n_pitems, w.scalars,
+                                      w.perm, w.pq, p->status);
+        });
+    } else {
+        run(s, KC_BIN, [&] { return launch_bin(s, ca, pos, q, w.cell_of, w.counts, w.qpart, p->status); });
+        run(s, KC_SCAN, [&] {
+            return launch_scan(s, ca, w.counts, w.fill, w.cell_start, w.qpart, nqb, w.scalars, w.tile_sums,
+                               w.pitem_cell, w.pitem_off, w.n_pitems);
+        });
+        run(s, KC_SCATTER, [&] { return launch_scatter(s, ca, w.cell_of, w.cell_start, w.fill, w.tmp_idx); });
+        run(s, KC_CELLSORT,
+            [&] { return launch_cellsort(s, ca, w.cell_start, w.tmp_idx, pos, q, w.perm, w.pq); });
+    }
     const int max_pitems = p->ncell + ceil_div(n, kPairHome);
     run(s, KC_PAIRLIST, [&] {
         return launch_pair_list(s, pa, max_pitems, w.n_pitems, w.pitem_cell, w.pitem_off, w.cell_start, w.pq,
@@ -884,13 +892,20 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
 
     // Join, then the totals.
     if (!one_stream && e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_join, 0);
-    run(s, KC_FINAL_P, [&] {
-        return launch_finalize_particles(s, fa, w.pq, w.perm, w.freal, w.gpart, w.scalars, forces, dEdq,
-                                         w.epart);
-    });
-    run(s, KC_FINAL_E, [&] {
-        return launch_finalize_energy(s, fa, w.epart, ceil_div(n, 256), w.erec, w.scalars, p->status, energy);
-    });
+    if (finalize_small(n)) {  // one workgroup, same sums
+        run(s, KC_FINAL_P, [&] {
+            return launch_finalize_small(s, fa, w.pq, w.perm, w.freal, w.gpart, w.scalars, forces, dEdq, w.erec,
+                                         p->status, energy);
+        });
+    } else {
+        run(s, KC_FINAL_P, [&] {
+            return launch_finalize_particles(s, fa, w.pq, w.perm, w.freal, w.gpart, w.scalars, forces, dEdq,
+                                             w.epart);
+        });
+        run(s, KC_FINAL_E, [&] {
+            return launch_finalize_energy(s, fa, w.epart, ceil_div(n, 256), w.erec, w.scalars, p->status, energy);
+        });
+    }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return EWALD_ERR_DEVICE;
