@@ -331,13 +331,48 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
 constexpr int kSmallThreads = 1024;
 constexpr int kSmallIndexBits = 11;  // kSmallCellsMaxN = 2^11
 
+// Tree over the kBinThreads values of each group of kBinThreads threads, in the
+// order of k_bin's tree (t += t + w for w = 128, 64, ..., 1): the two widest
+// steps through LDS, the rest with shuffles inside the wave (lane t receives
+// lane t + w), so fewer barriers give the same sums.
+__device__ inline void group_tree256(double &a, double &b, double *s_a, double *s_b)
+{
+    const int t = (int)threadIdx.x, g = t % kBinThreads;
+    s_a[t] = a;
+    s_b[t] = b;
+    __syncthreads();
+    if (g < 128) {
+        s_a[t] += s_a[t + 128];
+        s_b[t] += s_b[t + 128];
+    }
+    __syncthreads();
+    if (g < 64) {
+        s_a[t] += s_a[t + 64];
+        s_b[t] += s_b[t + 64];
+    }
+    __syncthreads();
+    a = s_a[t];
+    b = s_b[t];
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) {
+        const double xa = __shfl_down(a, w), xb = __shfl_down(b, w);
+        if (g < w) {
+            a += xa;
+            b += xb;
+        }
+    }
+    __syncthreads();  // s_a, s_b may be refilled
+}
+
 // The whole cell list of a small system (n <= kSmallCellsMaxN, ncell <=
 // kSmallCellsMaxCells) in one workgroup, with the outputs of the four kernels
 // above bit for bit: the same cells, charge sums in the same order (trees over
 // 256-particle chunks as k_bin, then the tree of k_scan_tiles), the same
 // cell_start and pair-work items, and particles in cell order, input order
-// inside a cell (a bitonic sort of the keys cell << 11 | index in LDS).  One
-// launch instead of four, which is most of a small system's real-space path.
+// inside a cell.  A particle's place is the rank of its key cell << 11 | index
+// among all keys (counted against the keys in LDS, no sort and no barriers).
+// One launch instead of four, which is most of a small system's real-space
+// path.
 __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, int nc,
                                                                const double *__restrict__ pos,
                                                                const double *__restrict__ q,
@@ -348,6 +383,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, 
                                                                int *__restrict__ status)
 {
     __shared__ int s_key[kSmallCellsMaxN];
+    __shared__ d4 s_rec[kSmallCellsMaxN];  // wrapped position and charge
     __shared__ int s_cnt[kSmallCellsMaxCells];
     __shared__ double s_a[kSmallThreads], s_b[kSmallThreads];
     __shared__ double s_qp[2 * (kSmallCellsMaxN / kBinThreads)];
@@ -357,7 +393,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, 
     const int nq = (n + kBinThreads - 1) / kBinThreads;
     for (int c = t; c < ncell; c += kSmallThreads) s_cnt[c] = 0;
     __syncthreads();
-    // cells, keys and counts; charge partials of each chunk of kBinThreads
+    // cells, keys, counts and records; charge partials of each chunk of kBinThreads
     for (int base = 0; base < n; base += kSmallThreads) {
         const int i = base + t;
         double qi = 0.0;
@@ -365,56 +401,42 @@ __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, 
             const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
             qi = q[i];
             const bool fin = isfinite(x) && isfinite(y) && isfinite(z) && isfinite(qi);
+            d4 r;
+            r.a = wrap_coord(x, L);
+            r.b = wrap_coord(y, L);
+            r.c = wrap_coord(z, L);
+            r.d = qi;
             int c = 0;
             if (fin)
-                c = (cell_coord(wrap_coord(x, L), L, nc) * nc + cell_coord(wrap_coord(y, L), L, nc)) * nc +
-                    cell_coord(wrap_coord(z, L), L, nc);
+                c = (cell_coord(r.a, L, nc) * nc + cell_coord(r.b, L, nc)) * nc + cell_coord(r.c, L, nc);
             else
                 atomicOr(status, 1);
             s_key[i] = (c << kSmallIndexBits) | i;
+            s_rec[i] = r;
             atomicAdd(&s_cnt[c], 1);
         }
-        s_a[t] = qi;
-        s_b[t] = qi * qi;
-        __syncthreads();
-        const int g = t % kBinThreads;
-        for (int w = kBinThreads / 2; w > 0; w >>= 1) {
-            if (g < w) {
-                s_a[t] += s_a[t + w];
-                s_b[t] += s_b[t + w];
-            }
-            __syncthreads();
+        double a = qi, b = qi * qi;
+        group_tree256(a, b, s_a, s_b);
+        const int blk = (base + t) / kBinThreads;
+        if (t % kBinThreads == 0 && blk < nq) {
+            s_qp[2 * blk] = a;
+            s_qp[2 * blk + 1] = b;
         }
-        const int b = (base + t) / kBinThreads;
-        if (g == 0 && b < nq) {
-            s_qp[2 * b] = s_a[t];
-            s_qp[2 * b + 1] = s_b[t];
-        }
-        __syncthreads();
     }
+    __syncthreads();
     // Q and sum q^2 (k_scan_tiles' last block: chunk k on thread k, then a tree)
-    if (t < kScanThreads) {
+    {
         double a = 0.0, b = 0.0;
         if (t < nq) {
             a += s_qp[2 * t];
             b += s_qp[2 * t + 1];
         }
-        s_a[t] = a;
-        s_b[t] = b;
-    }
-    __syncthreads();
-    for (int w = kScanThreads / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            s_a[t] += s_a[t + w];
-            s_b[t] += s_b[t + w];
+        group_tree256(a, b, s_a, s_b);
+        if (t == 0) {
+            scalars[0] = a;
+            scalars[1] = b;
         }
-        __syncthreads();
     }
-    if (t == 0) {
-        scalars[0] = s_a[0];
-        scalars[1] = s_b[0];
-    }
-    bitonic_sort_block<kSmallThreads>(s_key, n);
     // exclusive scans of the counts and of the pair-work items, kScanPer cells
     // per thread (ncell <= kScanPer kSmallThreads)
     const int c0 = t * kScanPer;
@@ -467,16 +489,13 @@ __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, 
         cell_start[ncell] = ta;
         *n_items = tb;
     }
-    // records in cell order
-    for (int k = t; k < n; k += kSmallThreads) {
-        const int mine = s_key[k] & ((1 << kSmallIndexBits) - 1);
-        perm[k] = mine;
-        d4 r;
-        r.a = wrap_coord(pos[3 * (int64_t)mine], L);
-        r.b = wrap_coord(pos[3 * (int64_t)mine + 1], L);
-        r.c = wrap_coord(pos[3 * (int64_t)mine + 2], L);
-        r.d = q[mine];
-        pq[k] = r;
+    // records in cell order: the rank of each key among all keys
+    for (int i = t; i < n; i += kSmallThreads) {
+        const int mine = s_key[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) rank += s_key[j] < mine;
+        perm[rank] = i;
+        pq[rank] = s_rec[i];
     }
 }
 
