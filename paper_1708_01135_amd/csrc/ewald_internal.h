@@ -89,8 +89,11 @@ hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, 
                           int *fill, int *tmp_idx);
 // One-workgroup cell list of a small system (n <= kSmallCellsMaxN, ncell <=
 // kSmallCellsMaxCells): the outputs of bin, scan, scatter and cellsort, bit
-// for bit (counts, fill and tile sums are not touched).
-constexpr int kSmallCellsMaxN = 2048;
+// for bit (counts, fill and tile sums are not touched).  Measured on
+// serving-mix electrolytes: 0.090 against 0.095 ms per call at 256 ions, even
+// at 512, 0.19 against 0.10 at 2048 (one workgroup's O(n^2) ranks and serial
+// chunks lose to the spread kernels).
+constexpr int kSmallCellsMaxN = 512;
 constexpr int kSmallCellsMaxCells = 4096;
 bool cells_small(const CellArgs &a);
 hipError_t launch_cells_small(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_start,
@@ -224,7 +227,7 @@ struct FinalArgs {
 hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
                                      const d4 *freal, const d4 *gpart, const double *scalars,
                                      double *forces, double *dEdq, double *epart);
-// Both totals passes in one workgroup for a small system (n <= 2048), with the
+// Both totals passes in one workgroup for a small system (n <= 512), with the
 // same sums in the same order as launch_finalize_particles + _energy.
 bool finalize_small(int64_t n);
 hipError_t launch_finalize_small(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm, const d4 *freal,

@@ -13,7 +13,7 @@
 //   scatter  : slot claim inside each cell (order not yet deterministic);
 //   cellsort : per cell, restore input order (rank, or sort the indices) and
 //              write the sorted records.
-// A small system (at most 2048 particles and 4096 cells) takes all four steps
+// A small system (at most 512 particles and 4096 cells) takes all four steps
 // in one workgroup (k_cells_small), with the same results.
 #include <algorithm>
 
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
 }
 
 constexpr int kSmallThreads = 1024;
-constexpr int kSmallIndexBits = 11;  // kSmallCellsMaxN = 2^11
+constexpr int kSmallIndexBits = 11;  // index bits of a key (>= log2 kSmallCellsMaxN)
 
 // Tree over the kBinThreads values of each group of kBinThreads threads, in the
 // order of k_bin's tree (t += t + w for w = 128, 64, ..., 1): the two widest

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void k_final_e(int n_epart, const double *__re
 // Both passes in one workgroup for n <= kSmallFinalMaxN: the blocks of k_final_p
 // one after the other, their partials kept in LDS, then k_final_e; the same
 // sums in the same order.
-constexpr int kSmallFinalMaxN = 2048;
+constexpr int kSmallFinalMaxN = 512;
 __global__ __launch_bounds__(256) void k_final_small(int64_t n, double L, double alpha, int n_split,
                                                      const d4 *__restrict__ pq, const int *__restrict__ perm,
                                                      const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
