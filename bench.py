@@ -126,6 +126,29 @@ def traffic_bytes(kernel, workload, precision):
     return None
 
 
+def issue_busy(kernel, workload, precision):
+    """(VALU busy, matrix busy) fractions of SIMD-cycles from the committed
+    counter summary, or None when absent or taken on a different kernel source.
+    The real-space chain weights its two kernels by their durations."""
+    path = os.path.join(ROOT, "profiles", "issue.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tab = json.load(f)
+    names = REALSPACE if kernel == "realspace" else (kernel,)
+    got = []
+    for name in names:
+        hit = [e for e in tab.get("entries", [])
+               if (e["kernel"], e["workload"], e["precision"]) == (name, workload, precision)]
+        if not hit or hit[0].get("source_sha256_16") != source_hash(name):
+            return None
+        got.append(hit[0])
+    w = sum(e["duration_us"] for e in got)
+    return {"valu_busy": sum(e["valu_busy"] * e["duration_us"] for e in got) / w,
+            "matrix_busy": sum(e["matrix_busy"] * e["duration_us"] for e in got) / w,
+            "source": "profiles/issue.json (kernel alone, rocprofv3 counters)"}
+
+
 def calib_copy(mib):
     import torch
     n = mib * 1024 * 1024 // 4
@@ -208,7 +231,7 @@ def rooflines(n, nk, prec, kern, stats, workload):
         bound, peak = kernel_bound(k, prec, stats)
         r = {"bound": bound, "kernel": k if k != "realspace" else "pair_list+pair", "achieved": ach, "peak": peak,
              "unit": "TFLOP/s", "frac": ach / peak, "traffic": traffic_bytes(k, workload, prec), "avg_ms": ms,
-             "algorithmic_flops_per_launch": flops}
+             "algorithmic_flops_per_launch": flops, "issue": issue_busy(k, workload, prec)}
         exe = {"sk": stats.get("sk_mfma_flops", 0), "gather": stats.get("gather_mfma_flops", 0)}.get(k, 0)
         if exe:
             r["executed_flops_per_launch"] = exe
