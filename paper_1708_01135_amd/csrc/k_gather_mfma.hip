@@ -16,10 +16,11 @@
 // LDS.  Lane l owns particle l % 16 of each sub-tile and, in output register
 // r, row 4 (l / 16) + r (FP32) or 4 r + l / 16 (FP64); the plan places quad
 // l / 16's n_y offset r there.  The phase P of the quad's first row comes from
-// one reduced FP64 argument and FP32 polynomials (FP32), or (FP64) from x^n
-// and y^n tables (0 <= n <= k_max) that the block builds in LDS for its
-// particles (FP64 recurrences from one sincos per eight powers): one complex
-// product instead of a library sincos per quad and particle.  The other three
+// one reduced FP64 argument and FP32 polynomials (FP32, 32-particle blocks),
+// or from x^n and y^n tables (0 <= n <= k_max) that the block builds in LDS
+// for its particles (FP64 recurrences from one sincos per eight powers; FP64,
+// and FP32 64-particle blocks): one complex product instead of a sincos per
+// quad and particle.  The other three
 // rows follow by a recurrence along n_y.  Sums over rows are FP64 per lane,
 // then reduced over the four lane groups and the block's waves in a fixed
 // order.
@@ -90,13 +91,16 @@ struct RC {
     R re, im;
 };
 
-// The FP64 gather takes its phases from LDS tables (a library FP64 sincos per
-// quad and particle cost more than building them); the FP32 one from
-// row_phase (measured: tables made it slower at rock salt 32^3).
-template <typename R>
+// Where the phases come from: LDS tables for the FP64 gather (a library FP64
+// sincos per quad and particle cost more than building them) and for FP32
+// blocks of 64 particles (large systems: a block then meets every tile, so the
+// tables' setup is spread over many epilogues; 64^3 took 1464 against 1521 us
+// per gather, rel_F 3.25e-7 either way); row_phase for FP32 blocks of 32
+// (tables made rock salt 32^3 slower).
+template <typename R, int NP>
 constexpr bool gather_tables()
 {
-    return sizeof(R) == 8;
+    return sizeof(R) == 8 || NP == 64;
 }
 
 // padded LDS stride of one k component for blocks of NP particles: the four
@@ -148,7 +152,7 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     }
 
     const double gk = 2.0 * kPi / L;
-    constexpr bool kTab = gather_tables<R>();
+    constexpr bool kTab = gather_tables<R, NP>();
     // FP64: x^n and y^n (n <= K) of the block's particles, entry (axis, n, col)
     // at ptab[(axis (K + 1) + n) NP + col].  Thread task (axis, block of eight
     // powers, col): one sincos at the block's first power and one for the
@@ -358,7 +362,7 @@ size_t gather_mfma_stage_bytes(int nap_max, int np, bool fp64)
 
 size_t gather_mfma_smem_bytes(int nap_max, int np, int K, bool fp64)
 {
-    const bool tables = fp64 ? gather_tables<double>() : gather_tables<float>();
+    const bool tables = fp64 ? gather_tables<double, 32>() : (np == 64 ? gather_tables<float, 64>() : gather_tables<float, 32>());
     const size_t tab = tables ? (size_t)2 * (K + 1) * np * (fp64 ? sizeof(RC<double>) : sizeof(RC<float>)) : 0;
     const size_t stage = gather_mfma_stage_bytes(nap_max, np, fp64) + tab;
     const size_t red = (size_t)kGmWaves * np * sizeof(d4);
