@@ -452,6 +452,7 @@ struct ewald_plan_s {
     // joined back to the caller's stream, concurrently with the real-space ones
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_phase = nullptr;  // the phase tables are written (see phase_first)
     hipEvent_t ev_done = nullptr;  // recorded after each graph launch on the plan's stream
     bool last_graph = false;       // the previous evaluation was a graph launch
     int device = 0;
@@ -674,8 +675,10 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
         hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&p->ev_phase, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_done, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
+        if (p->ev_phase) (void)hipEventDestroy(p->ev_phase);
         if (p->ev_join) (void)hipEventDestroy(p->ev_join);
         if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
         if (p->cap) (void)hipStreamDestroy(p->cap);
@@ -750,6 +753,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
         (void)hipGetLastError();
         (void)hipEventDestroy(p->ev_fork);
         (void)hipEventDestroy(p->ev_join);
+        (void)hipEventDestroy(p->ev_phase);
         (void)hipEventDestroy(p->ev_done);
         (void)hipStreamDestroy(p->cap);
         (void)hipStreamDestroy(p->aux);
@@ -776,6 +780,25 @@ namespace {
 // stream while a graph is recorded).  energy_only skips the force gather (the
 // reciprocal energy comes from the structure factor alone); gscale, when
 // given, turns the force / dE/dq outputs into the adjoint.
+// Whether the real-space chain waits for the phase tables.  Started together,
+// the real-space kernels (tens of thousands of small blocks) take the compute
+// units from the phase kernel: at 10^6 ions it ran 3.6 ms beside them against
+// 0.47 ms alone, on the reciprocal chain that sets the wall time.  Where the
+// reciprocal work dominates, waiting costs the real-space chain little.  A pair
+// costs about 31 (particle, k) terms (32^3: 114 us for 1.25e7 pairs against
+// 157 us for 5.5e8 terms); the wait is taken when the reciprocal chain is
+// estimated at three times the real-space one or more: |K+| ~ (2/3) pi K^3
+// against 3 x 31 x (4/3) pi r_c^3 n / L^3 pairs per particle.  Measured: 10^6
+// ions (ratio 3.9) 24.4 against 25.5 ms mixed, 33.0 against 33.9 FP64; 64^3
+// (ratio 2.1) gained nothing mixed and lost 2 % in FP64, so it does not wait.
+bool phase_first(const ewald_params &prm, int64_t n)
+{
+    const double L = prm.box_L, rc = prm.r_c, K = prm.k_max;
+    const double pairs = 4.0 / 3.0 * kPi * rc * rc * rc * (double)n / (L * L * L);
+    const double kvec = 2.0 / 3.0 * kPi * K * K * K;
+    return kvec > 3.0 * 31.0 * pairs;
+}
+
 ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_stream, int64_t n,
                          const double *pos, const double *q, double *energy, double *forces, double *dEdq,
                          const double *gscale, bool energy_only, bool allow_prof = true)
@@ -826,6 +849,10 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
     {
         auto *tx = static_cast<c64 *>(w.tx), *ty = static_cast<c64 *>(w.ty), *tz = static_cast<c64 *>(w.tz);
         run(ax, KC_PHASE, [&] { return launch_phase<double>(ax, ra, pos, q, w.pr, tx, ty, tz); });
+        if (!one_stream && e == hipSuccess && phase_first(p->prm, n)) {
+            e = hipEventRecord(p->ev_phase, ax);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, p->ev_phase, 0);
+        }
         run(ax, KC_SK, [&] {
             if (p->mfma_sk)
                 return launch_sk_mfma(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
@@ -1120,6 +1147,7 @@ void ewald_release(ewald_plan_t p)
             if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
         (void)hipEventDestroy(p->ev_fork);
         (void)hipEventDestroy(p->ev_join);
+        (void)hipEventDestroy(p->ev_phase);
         (void)hipEventDestroy(p->ev_done);
         (void)hipStreamDestroy(p->cap);
         (void)hipStreamDestroy(p->aux);
