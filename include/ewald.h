@@ -221,6 +221,46 @@ ewald_status ewald_energy_forces_ws(ewald_plan_t plan, int64_t n, const double *
                                     double *energy, double *forces, double *dEdq, void *workspace,
                                     size_t workspace_bytes);
 
+/* Most systems one ewald_energy_forces_batch() call takes. */
+#define EWALD_BATCH_MAX 1024
+
+/* ewald_energy_forces() of `count` independent systems in one launch
+ * sequence: each kernel of the path (section 3.2.1 real space, Eq. perf_mod1
+ * and Algorithms 1 and 2 reciprocal space, section 3.2.2 self and background
+ * terms) is launched once for all the systems, over a ragged work list in
+ * which every system owns a contiguous range of the launch's workgroups, in
+ * place of count launches.  Systems may differ in n, box, alpha, r_c, k_max
+ * and precision; those whose shapes select different kernel instances or
+ * block sizes share the step's launch order but not a launch, and at most a
+ * kernel's pack of argument structs (8 or more systems) goes into one launch.
+ *   plans[i]             plan of system i; all on one device.
+ *   n[i], pos[i], q[i], energy[i], forces[i], dEdq[i]
+ *                        as for ewald_energy_forces() (forces and dEdq may be
+ *                        NULL arrays, or hold NULL entries).
+ *   workspace[i]         device, 256-byte aligned, at least
+ *                        ewald_eval_workspace_bytes(plans[i], n[i]) bytes
+ *                        (workspace_bytes[i] says how many): system i's
+ *                        per-evaluation buffers.  May be a NULL array or hold
+ *                        NULL: then the plan's own buffers are used, and that
+ *                        plan (made without EWALD_FLAG_NO_WORKSPACE) is used
+ *                        by no other NULL-workspace entry of the batch.
+ *   stream               hipStream_t the whole batch is enqueued on (NULL: the
+ *                        null stream); the plans' own streams are not used, so
+ *                        no earlier call on a plan may still be running on
+ *                        another stream, and ewald_plan_status() is read after
+ *                        synchronising this one.
+ * Each system's results are bitwise those of ewald_energy_forces_ws() on the
+ * same inputs: every workgroup runs the same code on the same arguments.
+ * Allocates nothing; the launch descriptors travel in the kernel arguments.
+ * No graph replay and no profiling.  INVALID_ARG for count outside 1 ..
+ * EWALD_BATCH_MAX, a NULL or mis-aligned pointer, plans on different devices,
+ * or a plan's own buffers named twice; CAPACITY for n above a plan's n_max or
+ * a workspace that is too small; nothing is enqueued on either. */
+ewald_status ewald_energy_forces_batch(int32_t count, const ewald_plan_t *plans, const int64_t *n,
+                                       const double *const *pos, const double *const *q, double *const *energy,
+                                       double *const *forces, double *const *dEdq, void *const *workspace,
+                                       const size_t *workspace_bytes, void *stream);
+
 /* Allocation-free variant of ewald_energy_forces(), for callers that cannot
  * allocate device memory while they evaluate: code under HIP graph capture,
  * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,

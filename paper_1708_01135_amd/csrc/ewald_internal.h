@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -238,6 +240,106 @@ hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const doubl
                                   double *energy);
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---- one launch per system, or one launch for many systems ----
+// Every kernel is a plain struct of its arguments with
+//   static constexpr int kThreads;               block size
+//   static constexpr int kWavesPerEu;            waves per SIMD the registers must allow (1: no bound)
+//   __device__ void run(int bx, int by) const;   the work of block (bx, by)
+//   hipError_t one(stream, grid, threads, smem) const;
+//                                                launch of a plain kernel, with the
+//                                                same parameters, that calls the same code
+// one() keeps the parameters as kernel arguments, whose no-alias
+// qualifiers let the compiler turn uniform loads into scalar ones; a
+// pointer read from a struct would lose that.  k_many runs the structs of up to
+// BatchPack<K>::kCap systems in one 1-D grid over a ragged work list: system s
+// owns the blocks [span[s].first, span[s + 1].first), laid out gx = span[s].gx
+// wide, and block b of the launch runs block ((b - first) % gx, (b - first) /
+// gx) of its system.  The structs travel in the kernel arguments (at most
+// kBatchKernargBytes), so a batch needs no device memory and no copy of its
+// own.  Both kernels run the same body, so a system's results do not depend
+// on which launch ran it.
+struct BatchSpan {
+    int first;
+    int gx;
+};
+constexpr size_t kBatchKernargBytes = 4096;
+
+template <class K>
+struct BatchPack {
+    static constexpr int kCap = (int)((kBatchKernargBytes - 2 * sizeof(BatchSpan) - 8) / (sizeof(K) + sizeof(BatchSpan)));
+    K ks[kCap];
+    BatchSpan span[kCap + 1];
+    int nsys;
+};
+
+template <class K>
+__global__ __attribute__((amdgpu_flat_work_group_size(1, K::kThreads), amdgpu_waves_per_eu(K::kWavesPerEu))) void
+k_many(BatchPack<K> pk)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = pk.nsys;  // span[lo].first <= b < span[hi].first
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pk.span[mid].first <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const int local = b - pk.span[lo].first, gx = pk.span[lo].gx;
+    pk.ks[lo].run(local % gx, local / gx);
+}
+
+// A launch held for a batch instead of being enqueued (see BatchRecorder), and
+// the layout of its kernel's BatchPack.
+struct LaunchRecord {
+    const void *many;   // host stub of k_many<K>
+    int threads;
+    dim3 grid;
+    size_t smem;
+    size_t args_off;    // K's bytes in BatchRecorder::args
+    size_t args_size;   // sizeof(K)
+    int cap;            // BatchPack<K>::kCap
+    size_t span_off, nsys_off, pack_size;
+    int kind;           // rank of the launch's kernel class in the launch order
+    int occ;            // earlier launches of this system in the same class
+    int sys;
+};
+// While a host thread has a recorder installed (batch evaluation), launch()
+// appends to it instead of launching.
+struct BatchRecorder {
+    std::vector<LaunchRecord> recs;
+    std::vector<unsigned char> args;
+    int kind = 0;
+    int sys = 0;
+    int occ = 0;
+    void add(const LaunchRecord &r, const void *k);
+};
+extern thread_local BatchRecorder *t_batch;
+
+// threads: the block size, at most K::kThreads
+template <class K>
+hipError_t launch(hipStream_t s, dim3 grid, int threads, size_t smem, const K &k)
+{
+    static_assert(std::is_trivially_copyable<K>::value, "kernel arguments are copied as bytes");
+    using Pack = BatchPack<K>;
+    static_assert(Pack::kCap >= 8 && sizeof(Pack) <= kBatchKernargBytes, "batch pack");
+    if (t_batch) {
+        LaunchRecord r{};
+        r.many = reinterpret_cast<const void *>(&k_many<K>);
+        r.threads = threads;
+        r.grid = grid;
+        r.smem = smem;
+        r.args_size = sizeof(K);
+        r.cap = Pack::kCap;
+        r.span_off = offsetof(Pack, span);
+        r.nsys_off = offsetof(Pack, nsys);
+        r.pack_size = sizeof(Pack);
+        t_batch->add(r, &k);
+        return hipSuccess;
+    }
+    return k.one(s, grid, threads, smem);
+}
 
 // Position reduced into [0, L) (NaN and infinities map to 0; they are flagged
 // separately).  Shared by the cell binning and the phase tables so that both

@@ -31,7 +31,7 @@ __device__ inline int cell_coord(double w, double L, int nc)
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-__global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc,
+__device__ __forceinline__ void bin_body(int bx, int by, int64_t n, double L, int nc,
                                                      const double *__restrict__ pos,
                                                      const double *__restrict__ q,
                                                      int *__restrict__ cell_of, int *__restrict__ counts,
@@ -39,7 +39,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc
 {
     __shared__ double s_q[kBinThreads];
     __shared__ double s_q2[kBinThreads];
-    const int64_t i = (int64_t)blockIdx.x * kBinThreads + threadIdx.x;
+    const int64_t i = (int64_t)bx * kBinThreads + threadIdx.x;
     double qi = 0.0;
     if (i < n) {
         const double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
@@ -66,9 +66,40 @@ __global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        qpart[2 * blockIdx.x] = s_q[0];
-        qpart[2 * blockIdx.x + 1] = s_q2[0];
+        qpart[2 * bx] = s_q[0];
+        qpart[2 * bx + 1] = s_q2[0];
     }
+}
+
+struct KBin {
+    static constexpr int kThreads = kBinThreads;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    double L;
+    int nc;
+    const double *pos;
+    const double *q;
+    int *cell_of;
+    int *counts;
+    double *qpart;
+    int *status;
+    __device__ void run(int bx, int by) const { bin_body(bx, by, n, L, nc, pos, q, cell_of, counts, qpart, status); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc,
+                                                     const double *__restrict__ pos,
+                                                     const double *__restrict__ q,
+                                                     int *__restrict__ cell_of, int *__restrict__ counts,
+                                                     double *__restrict__ qpart, int *__restrict__ status)
+{
+    bin_body(blockIdx.x, blockIdx.y, n, L, nc, pos, q, cell_of, counts, qpart, status);
+}
+
+hipError_t KBin::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_bin), grid, dim3(threads), smem, s, n, L, nc, pos, q, cell_of, counts, qpart, status);
+    return hipGetLastError();
 }
 
 constexpr int kScanThreads = 256;
@@ -114,7 +145,7 @@ __device__ inline int2 block_sum2(int a, int b, int2 *s_w)
 // particle and pair-work-item totals.  Block n_tiles (the last one) instead
 // reduces the per-block charge sums of the binning into scalars[0] = Q and
 // scalars[1] = sum q^2, in a fixed order (contiguous ranges, then a fixed tree).
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ncell, int n_tiles, const int *__restrict__ counts,
+__device__ __forceinline__ void scan_tiles_body(int bx, int by, int ncell, int n_tiles, const int *__restrict__ counts,
                                                              int2 *__restrict__ tile_sums,
                                                              const double *__restrict__ qpart, int n_qblocks,
                                                              double *__restrict__ scalars)
@@ -123,11 +154,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ncell, int n_ti
     __shared__ double s_a[kScanThreads];
     __shared__ double s_b[kScanThreads];
     const int t = (int)threadIdx.x;
-    if ((int)blockIdx.x < n_tiles) {
-        const int4 v = load_counts(counts, (int)blockIdx.x * kScanTile + t * kScanPer, ncell);
+    if ((int)bx < n_tiles) {
+        const int4 v = load_counts(counts, (int)bx * kScanTile + t * kScanPer, ncell);
         const int2 tot = block_sum2(v.x + v.y + v.z + v.w, items_of(v.x) + items_of(v.y) + items_of(v.z) + items_of(v.w),
                                     s_w);
-        if (t == 0) tile_sums[blockIdx.x] = tot;
+        if (t == 0) tile_sums[bx] = tot;
         return;
     }
     const int qper = (n_qblocks + kScanThreads - 1) / kScanThreads;
@@ -152,13 +183,41 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ncell, int n_ti
     }
 }
 
+struct KScanTiles {
+    static constexpr int kThreads = kScanThreads;
+    static constexpr int kWavesPerEu = 1;
+    int ncell;
+    int n_tiles;
+    const int *counts;
+    int2 *tile_sums;
+    const double *qpart;
+    int n_qblocks;
+    double *scalars;
+    __device__ void run(int bx, int by) const { scan_tiles_body(bx, by, ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ncell, int n_tiles, const int *__restrict__ counts,
+                                                             int2 *__restrict__ tile_sums,
+                                                             const double *__restrict__ qpart, int n_qblocks,
+                                                             double *__restrict__ scalars)
+{
+    scan_tiles_body(blockIdx.x, blockIdx.y, ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars);
+}
+
+hipError_t KScanTiles::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_scan_tiles), grid, dim3(threads), smem, s, ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars);
+    return hipGetLastError();
+}
+
 // Pass 2, one block per tile: the tile's offset is the sum of the earlier
 // tiles' totals; an exclusive scan of the counts inside the tile (wave
 // shuffles, then the waves' totals) gives cell_start, and the pair-loop work
 // items (one per cell and kPairHome home particles, in cell order) are written
 // at the matching item offsets as (cell, offset of the first home particle).  Counts and fill are cleared for the next
 // evaluation.  The last block writes cell_start[ncell] and the item count.
-__global__ __launch_bounds__(kScanThreads) void k_scan_cells(int ncell, int n_tiles, int *__restrict__ counts,
+__device__ __forceinline__ void scan_cells_body(int bx, int by, int ncell, int n_tiles, int *__restrict__ counts,
                                                              int *__restrict__ fill,
                                                              const int2 *__restrict__ tile_sums,
                                                              int *__restrict__ cell_start, int *__restrict__ item_cell,
@@ -166,7 +225,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_cells(int ncell, int n_ti
 {
     __shared__ int2 s_w[kScanThreads / kLanes];
     const int t = (int)threadIdx.x, lane = t % kLanes, wave = t / kLanes;
-    const int b = (int)blockIdx.x;
+    const int b = (int)bx;
     int pa = 0, pb = 0;
     for (int k = t; k < b; k += kScanThreads) {
         const int2 v = tile_sums[k];
@@ -229,15 +288,71 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_cells(int ncell, int n_ti
     }
 }
 
-__global__ __launch_bounds__(256) void k_scatter(int64_t n, const int *__restrict__ cell_of,
+struct KScanCells {
+    static constexpr int kThreads = kScanThreads;
+    static constexpr int kWavesPerEu = 1;
+    int ncell;
+    int n_tiles;
+    int *counts;
+    int *fill;
+    const int2 *tile_sums;
+    int *cell_start;
+    int *item_cell;
+    int *item_off;
+    int *n_items;
+    __device__ void run(int bx, int by) const { scan_cells_body(bx, by, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_cells(int ncell, int n_tiles, int *__restrict__ counts,
+                                                             int *__restrict__ fill,
+                                                             const int2 *__restrict__ tile_sums,
+                                                             int *__restrict__ cell_start, int *__restrict__ item_cell,
+                                                             int *__restrict__ item_off, int *__restrict__ n_items)
+{
+    scan_cells_body(blockIdx.x, blockIdx.y, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items);
+}
+
+hipError_t KScanCells::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_scan_cells), grid, dim3(threads), smem, s, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items);
+    return hipGetLastError();
+}
+
+__device__ __forceinline__ void scatter_body(int bx, int by, int64_t n, const int *__restrict__ cell_of,
                                                  const int *__restrict__ cell_start, int *__restrict__ fill,
                                                  int *__restrict__ tmp_idx)
 {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)bx * 256 + threadIdx.x;
     if (i >= n) return;
     const int c = cell_of[i];
     const int slot = cell_start[c] + atomicAdd(&fill[c], 1);
     tmp_idx[slot] = (int)i;
+}
+
+struct KScatter {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    const int *cell_of;
+    const int *cell_start;
+    int *fill;
+    int *tmp_idx;
+    __device__ void run(int bx, int by) const { scatter_body(bx, by, n, cell_of, cell_start, fill, tmp_idx); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(256) void k_scatter(int64_t n, const int *__restrict__ cell_of,
+                                                 const int *__restrict__ cell_start, int *__restrict__ fill,
+                                                 int *__restrict__ tmp_idx)
+{
+    scatter_body(blockIdx.x, blockIdx.y, n, cell_of, cell_start, fill, tmp_idx);
+}
+
+hipError_t KScatter::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_scatter), grid, dim3(threads), smem, s, n, cell_of, cell_start, fill, tmp_idx);
+    return hipGetLastError();
 }
 
 constexpr int kSortThreads = 128;
@@ -289,13 +404,13 @@ __device__ inline void bitonic_sort_block(V v, int cnt)
 // entries, in place in tmp_idx beyond), so that the rank is the position.
 // Either way the order is the same, and O(cnt log^2 cnt) bounds the work of
 // a crowded cell.
-__global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *__restrict__ cell_start,
+__device__ __forceinline__ void cellsort_body(int bx, int by, double L, const int *__restrict__ cell_start,
                                                            int *__restrict__ tmp_idx, const double *__restrict__ pos,
                                                            const double *__restrict__ q, int *__restrict__ perm,
                                                            d4 *__restrict__ pq)
 {
     __shared__ int s_idx[kSortLds];
-    const int c = blockIdx.x;
+    const int c = bx;
     const int start = cell_start[c];
     const int cnt = cell_start[c + 1] - start;
     const bool in_lds = cnt <= kSortLds;  // uniform over the workgroup
@@ -326,6 +441,34 @@ __global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *
         r.d = q[mine];
         pq[s] = r;
     }
+}
+
+struct KCellSort {
+    static constexpr int kThreads = kSortThreads;
+    static constexpr int kWavesPerEu = 1;
+    double L;
+    const int *cell_start;
+    int *tmp_idx;
+    const double *pos;
+    const double *q;
+    int *perm;
+    d4 *pq;
+    __device__ void run(int bx, int by) const { cellsort_body(bx, by, L, cell_start, tmp_idx, pos, q, perm, pq); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(kSortThreads) void k_cellsort(double L, const int *__restrict__ cell_start,
+                                                           int *__restrict__ tmp_idx, const double *__restrict__ pos,
+                                                           const double *__restrict__ q, int *__restrict__ perm,
+                                                           d4 *__restrict__ pq)
+{
+    cellsort_body(blockIdx.x, blockIdx.y, L, cell_start, tmp_idx, pos, q, perm, pq);
+}
+
+hipError_t KCellSort::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_cellsort), grid, dim3(threads), smem, s, L, cell_start, tmp_idx, pos, q, perm, pq);
+    return hipGetLastError();
 }
 
 constexpr int kSmallThreads = 1024;
@@ -373,7 +516,7 @@ __device__ inline void group_tree256(double &a, double &b, double *s_a, double *
 // among all keys (counted against the keys in LDS, no sort and no barriers).
 // One launch instead of four, which is most of a small system's real-space
 // path.
-__global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, int nc,
+__device__ __forceinline__ void cells_small_body(int bx, int by, int n, double L, int nc,
                                                                const double *__restrict__ pos,
                                                                const double *__restrict__ q,
                                                                int *__restrict__ cell_start,
@@ -499,12 +642,71 @@ __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, 
     }
 }
 
+struct KCellsSmall {
+    static constexpr int kThreads = kSmallThreads;
+    static constexpr int kWavesPerEu = 1;
+    int n;
+    double L;
+    int nc;
+    const double *pos;
+    const double *q;
+    int *cell_start;
+    int *item_cell;
+    int *item_off;
+    int *n_items;
+    double *scalars;
+    int *perm;
+    d4 *pq;
+    int *status;
+    __device__ void run(int bx, int by) const { cells_small_body(bx, by, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, int nc,
+                                                               const double *__restrict__ pos,
+                                                               const double *__restrict__ q,
+                                                               int *__restrict__ cell_start,
+                                                               int *__restrict__ item_cell, int *__restrict__ item_off,
+                                                               int *__restrict__ n_items, double *__restrict__ scalars,
+                                                               int *__restrict__ perm, d4 *__restrict__ pq,
+                                                               int *__restrict__ status)
+{
+    cells_small_body(blockIdx.x, blockIdx.y, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status);
+}
+
+hipError_t KCellsSmall::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_cells_small), grid, dim3(threads), smem, s, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status);
+    return hipGetLastError();
+}
+
 // Clears `words` 16-byte words (the counters and padding an evaluation expects
 // at zero, when its buffers come from memory another evaluation used).
-__global__ __launch_bounds__(256) void k_zero(uint4 *__restrict__ p, int64_t words)
+__device__ __forceinline__ void zero_body(int bx, uint4 *__restrict__ p, int64_t words, int blocks)
 {
     const uint4 z = {0u, 0u, 0u, 0u};
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256) p[i] = z;
+    for (int64_t i = (int64_t)bx * 256 + threadIdx.x; i < words; i += (int64_t)blocks * 256) p[i] = z;
+}
+
+struct KZero {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    uint4 *p;
+    int64_t words;
+    int blocks;  // the launch's grid
+    __device__ void run(int bx, int) const { zero_body(bx, p, words, blocks); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(256) void k_zero(uint4 *__restrict__ p, int64_t words, int blocks)
+{
+    zero_body(blockIdx.x, p, words, blocks);
+}
+
+hipError_t KZero::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL(k_zero, grid, dim3(threads), smem, s, p, words, blocks);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -514,16 +716,14 @@ hipError_t launch_zero(hipStream_t s, void *p, size_t bytes)
     const int64_t words = (int64_t)(bytes / sizeof(uint4));
     if (words == 0) return hipSuccess;
     const int blocks = (int)std::min<int64_t>(ceil_div(words, 256), 2048);
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, static_cast<uint4 *>(p), words);
-    return hipGetLastError();
+    return launch(s, dim3(blocks), 256, 0, KZero{static_cast<uint4 *>(p), words, blocks});
 }
 
 hipError_t launch_bin(hipStream_t s, const CellArgs &a, const double *pos, const double *q, int *cell_of,
                       int *counts, double *qpart, int *status)
 {
-    hipLaunchKernelGGL(k_bin, dim3(ceil_div(a.n, kBinThreads)), dim3(kBinThreads), 0, s, a.n, a.L, a.nc, pos,
-                       q, cell_of, counts, qpart, status);
-    return hipGetLastError();
+    return launch(s, dim3(ceil_div(a.n, kBinThreads)), kBinThreads, 0,
+                  KBin{a.n, a.L, a.nc, pos, q, cell_of, counts, qpart, status});
 }
 
 hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill, int *cell_start,
@@ -531,13 +731,11 @@ hipError_t launch_scan(hipStream_t s, const CellArgs &a, int *counts, int *fill,
                        int *item_off, int *n_items)
 {
     const int n_tiles = scan_tiles(a.ncell);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(n_tiles + 1), dim3(kScanThreads), 0, s, a.ncell, n_tiles, counts,
-                       tile_sums, qpart, n_qblocks, scalars);
-    hipError_t e = hipGetLastError();
+    const hipError_t e = launch(s, dim3(n_tiles + 1), kScanThreads, 0,
+                                KScanTiles{a.ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars});
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scan_cells, dim3(n_tiles), dim3(kScanThreads), 0, s, a.ncell, n_tiles, counts, fill,
-                       tile_sums, cell_start, item_cell, item_off, n_items);
-    return hipGetLastError();
+    return launch(s, dim3(n_tiles), kScanThreads, 0,
+                  KScanCells{a.ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items});
 }
 
 int scan_tiles(int ncell) { return ceil_div(ncell, kScanTile); }
@@ -545,17 +743,13 @@ int scan_tiles(int ncell) { return ceil_div(ncell, kScanTile); }
 hipError_t launch_scatter(hipStream_t s, const CellArgs &a, const int *cell_of, const int *cell_start,
                           int *fill, int *tmp_idx)
 {
-    hipLaunchKernelGGL(k_scatter, dim3(ceil_div(a.n, 256)), dim3(256), 0, s, a.n, cell_of, cell_start, fill,
-                       tmp_idx);
-    return hipGetLastError();
+    return launch(s, dim3(ceil_div(a.n, 256)), 256, 0, KScatter{a.n, cell_of, cell_start, fill, tmp_idx});
 }
 
 hipError_t launch_cellsort(hipStream_t s, const CellArgs &a, const int *cell_start, int *tmp_idx,
                            const double *pos, const double *q, int *perm, d4 *pq)
 {
-    hipLaunchKernelGGL(k_cellsort, dim3(a.ncell), dim3(kSortThreads), 0, s, a.L, cell_start, tmp_idx, pos, q,
-                       perm, pq);
-    return hipGetLastError();
+    return launch(s, dim3(a.ncell), kSortThreads, 0, KCellSort{a.L, cell_start, tmp_idx, pos, q, perm, pq});
 }
 
 int bin_blocks(int64_t n) { return ceil_div(n, kBinThreads); }
@@ -566,9 +760,9 @@ hipError_t launch_cells_small(hipStream_t s, const CellArgs &a, const double *po
                               int *item_cell, int *item_off, int *n_items, double *scalars, int *perm, d4 *pq,
                               int *status)
 {
-    hipLaunchKernelGGL(k_cells_small, dim3(1), dim3(kSmallThreads), 0, s, (int)a.n, a.L, a.nc, pos, q, cell_start,
-                       item_cell, item_off, n_items, scalars, perm, pq, status);
-    return hipGetLastError();
+    return launch(s, dim3(1), kSmallThreads, 0,
+                  KCellsSmall{(int)a.n, a.L, a.nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm,
+                              pq, status});
 }
 
 }  // namespace ewk

@@ -62,7 +62,7 @@ __device__ inline double block_tree256(double *sh)
     return sh[0];
 }
 
-__global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alpha, int n_split,
+__device__ __forceinline__ void final_p_body(int bx, int by, int64_t n, double L, double alpha, int n_split,
                                                  const d4 *__restrict__ pq, const int *__restrict__ perm,
                                                  const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
                                                  const double *__restrict__ scalars, const double *__restrict__ gscale,
@@ -70,10 +70,46 @@ __global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alp
                                                  double *__restrict__ epart)
 {
     __shared__ double s_e[256];
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t s = (int64_t)bx * 256 + threadIdx.x;
     s_e[threadIdx.x] = final_particle(s, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq);
     const double e = block_tree256(s_e);
-    if (threadIdx.x == 0) epart[blockIdx.x] = e;
+    if (threadIdx.x == 0) epart[bx] = e;
+}
+
+struct KFinalP {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    double L;
+    double alpha;
+    int n_split;
+    const d4 *pq;
+    const int *perm;
+    const d4 *freal;
+    const d4 *gpart;
+    const double *scalars;
+    const double *gscale;
+    double *forces;
+    double *dEdq;
+    double *epart;
+    __device__ void run(int bx, int by) const { final_p_body(bx, by, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alpha, int n_split,
+                                                 const d4 *__restrict__ pq, const int *__restrict__ perm,
+                                                 const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
+                                                 const double *__restrict__ scalars, const double *__restrict__ gscale,
+                                                 double *__restrict__ forces, double *__restrict__ dEdq,
+                                                 double *__restrict__ epart)
+{
+    final_p_body(blockIdx.x, blockIdx.y, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart);
+}
+
+hipError_t KFinalP::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_final_p), grid, dim3(threads), smem, s, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart);
+    return hipGetLastError();
 }
 
 __device__ inline double ordered_block_sum(const double *__restrict__ v, int count, double *sh)
@@ -122,7 +158,7 @@ __device__ inline void final_energy(int n_epart, const double *epart, int n_erec
     }
 }
 
-__global__ __launch_bounds__(256) void k_final_e(int n_epart, const double *__restrict__ epart, int n_erec,
+__device__ __forceinline__ void final_e_body(int bx, int by, int n_epart, const double *__restrict__ epart, int n_erec,
                                                  const double *__restrict__ erec, double L, double alpha,
                                                  const double *__restrict__ scalars, int *__restrict__ status,
                                                  double *__restrict__ energy)
@@ -131,11 +167,41 @@ __global__ __launch_bounds__(256) void k_final_e(int n_epart, const double *__re
     final_energy(n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy, sh);
 }
 
+struct KFinalE {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    int n_epart;
+    const double *epart;
+    int n_erec;
+    const double *erec;
+    double L;
+    double alpha;
+    const double *scalars;
+    int *status;
+    double *energy;
+    __device__ void run(int bx, int by) const { final_e_body(bx, by, n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(256) void k_final_e(int n_epart, const double *__restrict__ epart, int n_erec,
+                                                 const double *__restrict__ erec, double L, double alpha,
+                                                 const double *__restrict__ scalars, int *__restrict__ status,
+                                                 double *__restrict__ energy)
+{
+    final_e_body(blockIdx.x, blockIdx.y, n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy);
+}
+
+hipError_t KFinalE::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_final_e), grid, dim3(threads), smem, s, n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy);
+    return hipGetLastError();
+}
+
 // Both passes in one workgroup for n <= kSmallFinalMaxN: the blocks of k_final_p
 // one after the other, their partials kept in LDS, then k_final_e; the same
 // sums in the same order.
 constexpr int kSmallFinalMaxN = 512;
-__global__ __launch_bounds__(256) void k_final_small(int64_t n, double L, double alpha, int n_split,
+__device__ __forceinline__ void final_small_body(int bx, int by, int64_t n, double L, double alpha, int n_split,
                                                      const d4 *__restrict__ pq, const int *__restrict__ perm,
                                                      const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
                                                      const double *__restrict__ scalars,
@@ -159,15 +225,55 @@ __global__ __launch_bounds__(256) void k_final_small(int64_t n, double L, double
     final_energy(nb, s_part, n_erec, erec, L, alpha, scalars, status, energy, s_e);
 }
 
+struct KFinalSmall {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    double L;
+    double alpha;
+    int n_split;
+    const d4 *pq;
+    const int *perm;
+    const d4 *freal;
+    const d4 *gpart;
+    const double *scalars;
+    const double *gscale;
+    double *forces;
+    double *dEdq;
+    int n_erec;
+    const double *erec;
+    int *status;
+    double *energy;
+    __device__ void run(int bx, int by) const { final_small_body(bx, by, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec, erec, status, energy); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(256) void k_final_small(int64_t n, double L, double alpha, int n_split,
+                                                     const d4 *__restrict__ pq, const int *__restrict__ perm,
+                                                     const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
+                                                     const double *__restrict__ scalars,
+                                                     const double *__restrict__ gscale, double *__restrict__ forces,
+                                                     double *__restrict__ dEdq, int n_erec,
+                                                     const double *__restrict__ erec, int *__restrict__ status,
+                                                     double *__restrict__ energy)
+{
+    final_small_body(blockIdx.x, blockIdx.y, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec, erec, status, energy);
+}
+
+hipError_t KFinalSmall::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_final_small), grid, dim3(threads), smem, s, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec, erec, status, energy);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4 *pq, const int *perm,
                                      const d4 *freal, const d4 *gpart, const double *scalars, double *forces,
                                      double *dEdq, double *epart)
 {
-    hipLaunchKernelGGL(k_final_p, dim3(ceil_div(a.n, 256)), dim3(256), 0, s, a.n, a.L, a.alpha, a.n_split, pq, perm,
-                       freal, gpart, scalars, a.gscale, forces, dEdq, epart);
-    return hipGetLastError();
+    return launch(s, dim3(ceil_div(a.n, 256)), 256, 0,
+                  KFinalP{a.n, a.L, a.alpha, a.n_split, pq, perm, freal, gpart, scalars, a.gscale, forces, dEdq, epart});
 }
 
 bool finalize_small(int64_t n) { return n <= kSmallFinalMaxN; }
@@ -176,18 +282,17 @@ hipError_t launch_finalize_small(hipStream_t s, const FinalArgs &a, const d4 *pq
                                  const d4 *gpart, const double *scalars, double *forces, double *dEdq,
                                  const double *erec_part, const int *status, double *energy)
 {
-    hipLaunchKernelGGL(k_final_small, dim3(1), dim3(256), 0, s, a.n, a.L, a.alpha, a.n_split, pq, perm, freal, gpart,
-                       scalars, a.gscale, forces, dEdq, a.n_erec, erec_part, const_cast<int *>(status), energy);
-    return hipGetLastError();
+    return launch(s, dim3(1), 256, 0,
+                  KFinalSmall{a.n, a.L, a.alpha, a.n_split, pq, perm, freal, gpart, scalars, a.gscale, forces, dEdq,
+                              a.n_erec, erec_part, const_cast<int *>(status), energy});
 }
 
 hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const double *epart, int n_epart,
                                   const double *erec_part, const double *scalars, const int *status,
                                   double *energy)
 {
-    hipLaunchKernelGGL(k_final_e, dim3(1), dim3(256), 0, s, n_epart, epart, a.n_erec, erec_part, a.L, a.alpha,
-                       scalars, const_cast<int *>(status), energy);
-    return hipGetLastError();
+    return launch(s, dim3(1), 256, 0,
+                  KFinalE{n_epart, epart, a.n_erec, erec_part, a.L, a.alpha, scalars, const_cast<int *>(status), energy});
 }
 
 }  // namespace ewk

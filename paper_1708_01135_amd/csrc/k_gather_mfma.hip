@@ -108,8 +108,8 @@ constexpr bool gather_tables()
 constexpr int zs_stride(int np) { return np + 16; }
 
 template <typename R, int NP>
-__global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int K, int nap_max,
-                                                                  SplitTable split, const d4 *__restrict__ pq,
+__device__ __forceinline__ void gather_mfma_body(int bx, int by, int64_t n, double L, int KP, int K, int nap_max,
+                                                                  const SplitTable &split, const d4 *__restrict__ pq,
                                                                   const c64 *__restrict__ tz,
                                                                   const MTile *__restrict__ tiles,
                                                                   const R *__restrict__ coef, d4 *__restrict__ gpart)
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     const int lane = (int)threadIdx.x & (kLanes - 1);
     // wave index made visibly uniform: tile loads and loop control stay scalar
     const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kLanes);
-    const int64_t p0 = (int64_t)blockIdx.x * NP;
+    const int64_t p0 = (int64_t)bx * NP;
 
     // z powers of the block's particles: entry (p, k, col) = Re/Im z^(2p + k/2),
     // loaded eight per thread at a time (indices clamped in bounds, stores
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
     }
 
     const int g = lane >> 4;  // quad of this lane
-    const int lo = split.lo[blockIdx.y], hi = split.lo[blockIdx.y + 1];
+    const int lo = split.lo[by], hi = split.lo[by + 1];
     const R *zl = zs + g * ZS + (lane & 15);
     for (int t = lo + w; t < hi; t += kGmWaves) {
         const MTile tl = tiles[t];
@@ -349,8 +349,44 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
             o.d += v.d;
         }
         const int64_t j = p0 + col;
-        if (j < n) gpart[(size_t)blockIdx.y * n + j] = o;
+        if (j < n) gpart[(size_t)by * n + j] = o;
     }
+}
+
+template <typename R, int NP>
+struct KGatherMfma {
+    static constexpr int kThreads = kGmWaves * kLanes;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    double L;
+    int KP;
+    int K;
+    int nap_max;
+    SplitTable split;
+    const d4 *pq;
+    const c64 *tz;
+    const MTile *tiles;
+    const R *coef;
+    d4 *gpart;
+    __device__ void run(int bx, int by) const { gather_mfma_body<R, NP>(bx, by, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+template <typename R, int NP>
+__global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int K, int nap_max,
+                                                                  SplitTable split, const d4 *__restrict__ pq,
+                                                                  const c64 *__restrict__ tz,
+                                                                  const MTile *__restrict__ tiles,
+                                                                  const R *__restrict__ coef, d4 *__restrict__ gpart)
+{
+    gather_mfma_body<R, NP>(blockIdx.x, blockIdx.y, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart);
+}
+
+template <typename R, int NP>
+hipError_t KGatherMfma<R, NP>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_gather_mfma<R, NP>), grid, dim3(threads), smem, s, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -378,12 +414,10 @@ hipError_t launch_gather_mfma(hipStream_t s, const RecipArgs &a, int n_split, co
     const int blocks = ceil_div(a.n, np);
     const size_t smem = gather_mfma_smem_bytes(nap_max, np, a.K, fp64);
     if (np == 64)
-        hipLaunchKernelGGL((k_gather_mfma<R, 64>), dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L,
-                           a.KP, a.K, nap_max, split, pq, tz, tiles, mcoef, gpart);
-    else
-        hipLaunchKernelGGL((k_gather_mfma<R, 32>), dim3(blocks, n_split), dim3(kGmWaves * kLanes), smem, s, a.n, a.L,
-                           a.KP, a.K, nap_max, split, pq, tz, tiles, mcoef, gpart);
-    return hipGetLastError();
+        return launch(s, dim3(blocks, n_split), kGmWaves * kLanes, smem,
+                      KGatherMfma<R, 64>{a.n, a.L, a.KP, a.K, nap_max, split, pq, tz, tiles, mcoef, gpart});
+    return launch(s, dim3(blocks, n_split), kGmWaves * kLanes, smem,
+                  KGatherMfma<R, 32>{a.n, a.L, a.KP, a.K, nap_max, split, pq, tz, tiles, mcoef, gpart});
 }
 
 template hipError_t launch_gather_mfma<float>(hipStream_t, const RecipArgs &, int, const SplitTable &, int,

@@ -203,7 +203,7 @@ __device__ inline int wrap_count(int v, int nc, int &w)
 // further kStreamSeg candidates of a larger neighbourhood).
 constexpr int kStreamSeg = 2048;
 
-__global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
+__device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L, double rc2, int max_items,
                                                   const int *__restrict__ n_items,
                                                   const int *__restrict__ item_cell, const int *__restrict__ item_off,
                                                   const int *__restrict__ cell_start, const d4 *__restrict__ pq,
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     // (known on the device only), so that padding blocks do not pile up on one XCD
     const int nit = *n_items;
     const int per = (nit + kXcds - 1) / kXcds;
-    if ((int)blockIdx.x >= per * kXcds) return;
-    const int it = xcd_remap(blockIdx.x, nit);
+    if ((int)bx >= per * kXcds) return;
+    const int it = xcd_remap(bx, nit);
     if (it >= nit) return;
     (void)max_items;
     const int lane = (int)threadIdx.x;
@@ -362,10 +362,44 @@ __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, 
     }
 }
 
+struct KPairList {
+    static constexpr int kThreads = 64;
+    static constexpr int kWavesPerEu = 1;
+    int nc;
+    double L;
+    double rc2;
+    int max_items;
+    const int *n_items;
+    const int *item_cell;
+    const int *item_off;
+    const int *cell_start;
+    const d4 *pq;
+    uint32_t *list;
+    int *list_cnt;
+    int cap;
+    __device__ void run(int bx, int by) const { pair_list_body(bx, by, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
+                                                  const int *__restrict__ n_items,
+                                                  const int *__restrict__ item_cell, const int *__restrict__ item_off,
+                                                  const int *__restrict__ cell_start, const d4 *__restrict__ pq,
+                                                  uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
+{
+    pair_list_body(blockIdx.x, blockIdx.y, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+}
+
+hipError_t KPairList::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_pair_list), grid, dim3(threads), smem, s, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    return hipGetLastError();
+}
+
 // Evaluation pass: a work item is any kPairHome consecutive particles (lists
 // carry global indices and image-shift codes, so no per-cell table is needed).
 template <bool MIXED, bool FIT64>
-__global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double rc2, double alpha,
+__device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, double L, double rc2, double alpha,
                                              const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                              const uint32_t *__restrict__ list, const int *__restrict__ list_cnt,
                                              int cap, d4 *__restrict__ freal)
@@ -382,7 +416,7 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
     __syncthreads();
     const int h = lane / kSub, s = lane % kSub;
     const int blocks = (int)((n + kPairHome - 1) / kPairHome);
-    const int64_t i = (int64_t)xcd_remap(blockIdx.x, blocks) * kPairHome + h;
+    const int64_t i = (int64_t)xcd_remap(bx, blocks) * kPairHome + h;
     const bool act = i < n;
     const d4 me = pq[act ? i : 0];
     const int cnt = act ? list_cnt[i] : 0;
@@ -472,15 +506,50 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
     }
 }
 
+template <bool MIXED, bool FIT64>
+struct KPair {
+    static constexpr int kThreads = 64;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    int nc;
+    double L;
+    double rc2;
+    double alpha;
+    const int *cell_start;
+    const d4 *pq;
+    const uint32_t *list;
+    const int *list_cnt;
+    int cap;
+    d4 *freal;
+    __device__ void run(int bx, int by) const { pair_body<MIXED, FIT64>(bx, by, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+template <bool MIXED, bool FIT64>
+__global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double rc2, double alpha,
+                                             const int *__restrict__ cell_start, const d4 *__restrict__ pq,
+                                             const uint32_t *__restrict__ list, const int *__restrict__ list_cnt,
+                                             int cap, d4 *__restrict__ freal)
+{
+    pair_body<MIXED, FIT64>(blockIdx.x, blockIdx.y, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
+}
+
+template <bool MIXED, bool FIT64>
+hipError_t KPair<MIXED, FIT64>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_pair<MIXED, FIT64>), grid, dim3(threads), smem, s, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, const int *n_items,
                             const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
                             uint32_t *list, int *list_cnt, int cap)
 {
-    hipLaunchKernelGGL(k_pair_list, dim3(xcd_grid(max_items)), dim3(64), 0, s, a.nc, a.L, a.rc2, max_items, n_items,
-                       item_cell, item_off, cell_start, pq, list, list_cnt, cap);
-    return hipGetLastError();
+    return launch(s, dim3(xcd_grid(max_items)), 64, 0,
+                  KPairList{a.nc, a.L, a.rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt,
+                            cap});
 }
 
 hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *cell_start, const d4 *pq,
@@ -490,15 +559,13 @@ hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *
     // the FP64 erfcx polynomial covers sqrt(alpha) r <= kErfcx64XMax
     const bool fit64 = sqrt(a.alpha * a.rc2) <= kErfcx64XMax;
     if (mixed)
-        hipLaunchKernelGGL((k_pair<true, false>), dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha,
-                           cell_start, pq, list, list_cnt, cap, freal);
-    else if (fit64)
-        hipLaunchKernelGGL((k_pair<false, true>), dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha,
-                           cell_start, pq, list, list_cnt, cap, freal);
-    else
-        hipLaunchKernelGGL((k_pair<false, false>), dim3(blocks), dim3(64), 0, s, a.n, a.nc, a.L, a.rc2, a.alpha,
-                           cell_start, pq, list, list_cnt, cap, freal);
-    return hipGetLastError();
+        return launch(s, dim3(blocks), 64, 0,
+                      KPair<true, false>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap, freal});
+    if (fit64)
+        return launch(s, dim3(blocks), 64, 0,
+                      KPair<false, true>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap, freal});
+    return launch(s, dim3(blocks), 64, 0,
+                  KPair<false, false>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap, freal});
 }
 
 }  // namespace ewk

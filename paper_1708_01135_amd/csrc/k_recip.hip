@@ -54,7 +54,7 @@ __device__ inline typename Cplx<R>::type make_c(double re, double im)
 // value).  The block's rows are staged in LDS and stored with consecutive
 // threads on consecutive entries.
 template <typename R>
-__global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
+__device__ __forceinline__ void phase_body(int bx, int by, int64_t n, double L, int KP, const double *__restrict__ pos,
                                                           const double *__restrict__ qv, d4 *__restrict__ pr,
                                                           typename Cplx<R>::type *__restrict__ tx,
                                                           typename Cplx<R>::type *__restrict__ ty,
@@ -67,8 +67,8 @@ __global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, i
     const int lr = (int)threadIdx.x >> 1, h = (int)threadIdx.x & 1;
     // grid row = axis: a block's rows are consecutive particles of one table,
     // so its write-out is one contiguous run
-    const int ax = (int)blockIdx.y;
-    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int ax = (int)by;
+    const int64_t r0 = (int64_t)bx * rows;
     const int64_t row = r0 + lr;
     if (row < n) {
         const int64_t j = row;
@@ -110,6 +110,40 @@ __global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, i
     const int count = (int)nrows * KP;
     C *out = (ax == 0 ? tx : (ax == 1 ? ty : tz)) + r0 * KP;
     for (int e = (int)threadIdx.x; e < count; e += (int)blockDim.x) out[e] = buf[e];
+}
+
+template <typename R>
+struct KPhase {
+    static constexpr int kThreads = 2 * kPhaseRows;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    double L;
+    int KP;
+    const double *pos;
+    const double *qv;
+    d4 *pr;
+    typename Cplx<R>::type *tx;
+    typename Cplx<R>::type *ty;
+    typename Cplx<R>::type *tz;
+    __device__ void run(int bx, int by) const { phase_body<R>(bx, by, n, L, KP, pos, qv, pr, tx, ty, tz); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+template <typename R>
+__global__ __launch_bounds__(2 * kPhaseRows) void k_phase(int64_t n, double L, int KP, const double *__restrict__ pos,
+                                                          const double *__restrict__ qv, d4 *__restrict__ pr,
+                                                          typename Cplx<R>::type *__restrict__ tx,
+                                                          typename Cplx<R>::type *__restrict__ ty,
+                                                          typename Cplx<R>::type *__restrict__ tz)
+{
+    phase_body<R>(blockIdx.x, blockIdx.y, n, L, KP, pos, qv, pr, tx, ty, tz);
+}
+
+template <typename R>
+hipError_t KPhase<R>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_phase<R>), grid, dim3(threads), smem, s, n, L, KP, pos, qv, pr, tx, ty, tz);
+    return hipGetLastError();
 }
 
 // --------------------------------------------------------------------- k_sk
@@ -163,7 +197,7 @@ __device__ inline void sk_fma(const c64 (&z)[kQ], const c64 &a, const c64 &b, do
 }
 
 
-__global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_len, int ts, int KP, int K1,
+__device__ __forceinline__ void sk_body(int bx, int by, int64_t n, int chunk_len, int ts, int KP, int K1,
                                                          const c64 *__restrict__ tx, const c64 *__restrict__ ty,
                                                          const c64 *__restrict__ tz,
                                                          const int *__restrict__ unit_group,
@@ -181,7 +215,7 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
 
     // logical block = chunk * n_units + unit, placed so that all units of a
     // chunk (which share its phase tables) run on one XCD
-    const int lb = xcd_remap(blockIdx.x, n_units * n_chunks);
+    const int lb = xcd_remap(bx, n_units * n_chunks);
     if (lb >= n_units * n_chunks) return;
     const int u = lb % n_units;
     const int chunk = lb / n_units;
@@ -307,11 +341,52 @@ __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_le
     }
 }
 
+struct KSk {
+    static constexpr int kThreads = kSkWaves *kLanes;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    int chunk_len;
+    int ts;
+    int KP;
+    int K1;
+    const c64 *tx;
+    const c64 *ty;
+    const c64 *tz;
+    const int *unit_group;
+    const int *unit_seg;
+    const int *row_nx;
+    const int *row_ny;
+    int n_rows;
+    int n_units;
+    int n_chunks;
+    d4 *part;
+    __device__ void run(int bx, int by) const { sk_body(bx, by, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units, n_chunks, part); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+__global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_len, int ts, int KP, int K1,
+                                                         const c64 *__restrict__ tx, const c64 *__restrict__ ty,
+                                                         const c64 *__restrict__ tz,
+                                                         const int *__restrict__ unit_group,
+                                                         const int *__restrict__ unit_seg,
+                                                         const int *__restrict__ row_nx,
+                                                         const int *__restrict__ row_ny, int n_rows, int n_units,
+                                                         int n_chunks, d4 *__restrict__ part)
+{
+    sk_body(blockIdx.x, blockIdx.y, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units, n_chunks, part);
+}
+
+hipError_t KSk::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_sk), grid, dim3(threads), smem, s, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units, n_chunks, part);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------- k_sk_reduce
 constexpr int kRedLanes = kRedSlotLanes;  // lanes cooperating on one slot
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, int n_rows, const d4 *__restrict__ part,
+__device__ __forceinline__ void sk_reduce_body(int bx, int by, int n_chunks, int n_units, int n_rows, const d4 *__restrict__ part,
                                                    const int *__restrict__ unit_group,
                                                    const int *__restrict__ unit_seg, const int *__restrict__ row_nx,
                                                    const int *__restrict__ row_ny, const int *__restrict__ row_m,
@@ -329,7 +404,7 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
     constexpr int kWaveSlots = kLanes / kRedLanes;
     const int ln = (int)threadIdx.x % kLanes;
     const int sub = ln / kWaveSlots;
-    const int slot = blockIdx.x * (256 / kRedLanes) + ((int)threadIdx.x / kLanes) * kWaveSlots + ln % kWaveSlots;
+    const int slot = bx * (256 / kRedLanes) + ((int)threadIdx.x / kLanes) * kWaveSlots + ln % kWaveSlots;
     const int cslot = slot < n_slots ? slot : n_slots - 1;
     double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
     for (int c = sub; c < n_chunks; c += kRedLanes) {
@@ -414,7 +489,51 @@ __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, in
         if ((int)threadIdx.x < w) s_e[threadIdx.x] += s_e[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) erec_part[blockIdx.x] = s_e[0];
+    if (threadIdx.x == 0) erec_part[bx] = s_e[0];
+}
+
+template <typename R>
+struct KSkReduce {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    int n_chunks;
+    int n_units;
+    int n_rows;
+    const d4 *part;
+    const int *unit_group;
+    const int *unit_seg;
+    const int *row_nx;
+    const int *row_ny;
+    const int *row_m;
+    const int *row_item;
+    const double *ck;
+    d4 *sk;
+    R *rec;
+    R *mcoef;
+    const int *row_mbase;
+    double *erec_part;
+    __device__ void run(int bx, int by) const { sk_reduce_body<R>(bx, by, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, int n_rows, const d4 *__restrict__ part,
+                                                   const int *__restrict__ unit_group,
+                                                   const int *__restrict__ unit_seg, const int *__restrict__ row_nx,
+                                                   const int *__restrict__ row_ny, const int *__restrict__ row_m,
+                                                   const int *__restrict__ row_item, const double *__restrict__ ck,
+                                                   d4 *__restrict__ sk, R *__restrict__ rec,
+                                                   R *__restrict__ mcoef, const int *__restrict__ row_mbase,
+                                                   double *__restrict__ erec_part)
+{
+    sk_reduce_body<R>(blockIdx.x, blockIdx.y, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
+}
+
+template <typename R>
+hipError_t KSkReduce<R>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_sk_reduce<R>), grid, dim3(threads), smem, s, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
+    return hipGetLastError();
 }
 
 // ----------------------------------------------------------------- k_gather
@@ -458,14 +577,14 @@ __device__ inline void gather_fma(const R (&v)[16], const typename Cplx<R>::type
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, SplitTable split,
+__device__ __forceinline__ void gather_body(int bx, int by, int64_t n, double L, int KP, const SplitTable &split,
                                                 const d4 *__restrict__ pq, const c64 *__restrict__ tz,
                                                 const int *__restrict__ item_meta, const R *__restrict__ rec,
                                                 d4 *__restrict__ gpart)
 {
     using C = typename Cplx<R>::type;
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int sp = blockIdx.y;
+    const int64_t j = (int64_t)bx * 256 + threadIdx.x;
+    const int sp = by;
     const int i0 = split.lo[sp], i1 = split.lo[sp + 1];
     const int64_t jj = j < n ? j : n - 1;
     const d4 r = pq[jj];
@@ -539,6 +658,39 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, Spl
     }
 }
 
+template <typename R>
+struct KGather {
+    static constexpr int kThreads = 256;
+    static constexpr int kWavesPerEu = 1;
+    int64_t n;
+    double L;
+    int KP;
+    SplitTable split;
+    const d4 *pq;
+    const c64 *tz;
+    const int *item_meta;
+    const R *rec;
+    d4 *gpart;
+    __device__ void run(int bx, int by) const { gather_body<R>(bx, by, n, L, KP, split, pq, tz, item_meta, rec, gpart); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_gather(int64_t n, double L, int KP, SplitTable split,
+                                                const d4 *__restrict__ pq, const c64 *__restrict__ tz,
+                                                const int *__restrict__ item_meta, const R *__restrict__ rec,
+                                                d4 *__restrict__ gpart)
+{
+    gather_body<R>(blockIdx.x, blockIdx.y, n, L, KP, split, pq, tz, item_meta, rec, gpart);
+}
+
+template <typename R>
+hipError_t KGather<R>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_gather<R>), grid, dim3(threads), smem, s, n, L, KP, split, pq, tz, item_meta, rec, gpart);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 template <typename R>
@@ -555,10 +707,8 @@ hipError_t launch_phase(hipStream_t s, const RecipArgs &a, const double *pos, co
                         typename Cplx<R>::type *tx, typename Cplx<R>::type *ty, typename Cplx<R>::type *tz)
 {
     const int rows = phase_rows<R>(a.KP);
-    hipLaunchKernelGGL(k_phase<R>, dim3(ceil_div(a.n, rows), 3), dim3(2 * rows),
-                       (size_t)rows * a.KP * sizeof(typename Cplx<R>::type), s, a.n, a.L, a.KP, pos, q, pr, tx, ty,
-                       tz);
-    return hipGetLastError();
+    return launch(s, dim3(ceil_div(a.n, rows), 3), 2 * rows, (size_t)rows * a.KP * sizeof(typename Cplx<R>::type),
+                  KPhase<R>{a.n, a.L, a.KP, pos, q, pr, tx, ty, tz});
 }
 
 // LDS bytes of one structure-factor block: two staged tiles per wave, or the
@@ -585,10 +735,9 @@ hipError_t launch_sk(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_
 {
     const int K1 = a.K + 1;
     const int ts = sk_tile(K1);
-    hipLaunchKernelGGL(k_sk, dim3(xcd_grid(a.n_units * n_chunks)), dim3(kSkWaves * kLanes), sk_smem_bytes(ts, K1), s,
-                       a.n, chunk_len, ts, a.KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, a.n_rows,
-                       a.n_units, n_chunks, part);
-    return hipGetLastError();
+    return launch(s, dim3(xcd_grid(a.n_units * n_chunks)), kSkWaves * kLanes, sk_smem_bytes(ts, K1),
+                  KSk{a.n, chunk_len, ts, a.KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, a.n_rows,
+                      a.n_units, n_chunks, part});
 }
 
 template <typename R>
@@ -597,19 +746,17 @@ hipError_t launch_sk_reduce(hipStream_t s, const RecipArgs &a, int n_chunks, con
                             const int *row_item, const double *ck, d4 *sk, R *rec, R *mcoef, const int *row_mbase,
                             double *erec_part)
 {
-    hipLaunchKernelGGL(k_sk_reduce<R>, dim3(ceil_div(a.n_slots, 256 / kRedLanes)), dim3(256), 0, s, n_chunks, a.n_units,
-                       a.n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef,
-                       row_mbase, erec_part);
-    return hipGetLastError();
+    return launch(s, dim3(ceil_div(a.n_slots, 256 / kRedLanes)), 256, 0,
+                  KSkReduce<R>{n_chunks, a.n_units, a.n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m,
+                               row_item, ck, sk, rec, mcoef, row_mbase, erec_part});
 }
 
 template <typename R>
 hipError_t launch_gather(hipStream_t s, const RecipArgs &a, int n_split, const SplitTable &split, const d4 *pq,
                          const c64 *tz, const int *item_meta, const R *rec, d4 *gpart)
 {
-    hipLaunchKernelGGL(k_gather<R>, dim3(ceil_div(a.n, 256), n_split), dim3(256), 0, s, a.n, a.L, a.KP, split, pq,
-                       tz, item_meta, rec, gpart);
-    return hipGetLastError();
+    return launch(s, dim3(ceil_div(a.n, 256), n_split), 256, 0,
+                  KGather<R>{a.n, a.L, a.KP, split, pq, tz, item_meta, rec, gpart});
 }
 
 #define EWK_INSTANTIATE(R)                                                                                         \

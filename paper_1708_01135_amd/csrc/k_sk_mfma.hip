@@ -87,7 +87,7 @@ __device__ __forceinline__ void sk_tile_dispatch(int nap, const c64 *__restrict_
 // k_max < 2 kSmNapSmall, kSmNap otherwise): fewer accumulators leave more of
 // the SIMD's registers to the real-space kernels that run beside it.
 template <int NMAX>
-__global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int KP, int P, int n_rows, int n_rblocks,
+__device__ __forceinline__ void sk_mfma_body(int bx, int by, int64_t n, int KP, int P, int n_rows, int n_rblocks,
                                                               int n_chunks, int chunk_len, const c64 *__restrict__ tx,
                                                               const c64 *__restrict__ ty, const c64 *__restrict__ tz,
                                                               const int *__restrict__ row_nx,
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int 
 {
     extern __shared__ __align__(16) unsigned char smem[];  // two buffers of [3][P][KP]: q x^n, y^n, z^n
     const int nb = n_rblocks * n_chunks;
-    const int bid = xcd_remap(blockIdx.x, nb);
+    const int bid = xcd_remap(bx, nb);
     if (bid >= nb) return;  // padding block (uniform over the block)
     const int chunk = bid / n_rblocks, rblk = bid % n_rblocks;
     const int64_t j_lo = (int64_t)chunk * chunk_len;
@@ -190,6 +190,52 @@ __global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int 
     }
 }
 
+template <int NMAX>
+struct KSkMfma {
+    static constexpr int kThreads = kSmWaves *kLanes;
+    static constexpr int kWavesPerEu = 2;
+    int64_t n;
+    int KP;
+    int P;
+    int n_rows;
+    int n_rblocks;
+    int n_chunks;
+    int chunk_len;
+    const c64 *tx;
+    const c64 *ty;
+    const c64 *tz;
+    const int *row_nx;
+    const int *row_ny;
+    const int *row_m;
+    const int *unit_base;
+    const int *tile_of;
+    int n_slots;
+    d4 *part;
+    __device__ void run(int bx, int by) const { sk_mfma_body<NMAX>(bx, by, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part); }
+    hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
+};
+
+template <int NMAX>
+__global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int KP, int P, int n_rows, int n_rblocks,
+                                                              int n_chunks, int chunk_len, const c64 *__restrict__ tx,
+                                                              const c64 *__restrict__ ty, const c64 *__restrict__ tz,
+                                                              const int *__restrict__ row_nx,
+                                                              const int *__restrict__ row_ny,
+                                                              const int *__restrict__ row_m,
+                                                              const int *__restrict__ unit_base,
+                                                              const int *__restrict__ tile_of, int n_slots,
+                                                              d4 *__restrict__ part)
+{
+    sk_mfma_body<NMAX>(blockIdx.x, blockIdx.y, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part);
+}
+
+template <int NMAX>
+hipError_t KSkMfma<NMAX>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+{
+    hipLaunchKernelGGL((k_sk_mfma<NMAX>), grid, dim3(threads), smem, s, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 // Particles per staged sub-chunk (a multiple of 8: two quads per step).  The
@@ -224,15 +270,14 @@ hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_chunks, int c
 {
     const int P = sk_mfma_particles(a.KP);
     const int n_rblocks = sk_mfma_row_blocks(a.n_rows);
+    const dim3 grid(xcd_grid(n_rblocks * n_chunks));
     if (a.KP <= 2 * kSmNapSmall)
-        hipLaunchKernelGGL(k_sk_mfma<kSmNapSmall>, dim3(xcd_grid(n_rblocks * n_chunks)), dim3(kSmWaves * kLanes),
-                           sk_mfma_smem_bytes(a.KP), s, a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty,
-                           tz, row_nx, row_ny, row_m, unit_base, tile_of, a.n_slots, part);
-    else
-        hipLaunchKernelGGL(k_sk_mfma<kSmNap>, dim3(xcd_grid(n_rblocks * n_chunks)), dim3(kSmWaves * kLanes),
-                           sk_mfma_smem_bytes(a.KP), s, a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty,
-                           tz, row_nx, row_ny, row_m, unit_base, tile_of, a.n_slots, part);
-    return hipGetLastError();
+        return launch(s, grid, kSmWaves * kLanes, sk_mfma_smem_bytes(a.KP),
+                      KSkMfma<kSmNapSmall>{a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx,
+                                           row_ny, row_m, unit_base, tile_of, a.n_slots, part});
+    return launch(s, grid, kSmWaves * kLanes, sk_mfma_smem_bytes(a.KP),
+                  KSkMfma<kSmNap>{a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny,
+                                  row_m, unit_base, tile_of, a.n_slots, part});
 }
 
 }  // namespace ewk

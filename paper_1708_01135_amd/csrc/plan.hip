@@ -2,6 +2,7 @@
 // plan-time tables (k-set layout, C_k, cell grid), one device allocation for
 // all workspace, and the per-call launch sequence on the plan's stream.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -16,6 +17,20 @@ namespace ewk {
 const char *const kKernelClassNames[KC_COUNT] = {"bin",    "scan",   "scatter",  "cellsort", "phase",  "sk",
                                                  "sk_reduce", "gather", "pair_list", "pair", "final_p", "final_e"};
 int bin_blocks(int64_t n);
+
+thread_local BatchRecorder *t_batch = nullptr;
+
+void BatchRecorder::add(const LaunchRecord &rec, const void *k)
+{
+    LaunchRecord r = rec;
+    r.args_off = args.size();
+    r.kind = kind;
+    r.occ = occ++;
+    r.sys = sys;
+    const unsigned char *b = static_cast<const unsigned char *>(k);
+    args.insert(args.end(), b, b + r.args_size);
+    recs.push_back(r);
+}
 }  // namespace ewk
 
 namespace {
@@ -791,6 +806,18 @@ namespace {
 // against 3 x 31 x (4/3) pi r_c^3 n / L^3 pairs per particle.  Measured: 10^6
 // ions (ratio 3.9) 24.4 against 25.5 ms mixed, 33.0 against 33.9 FP64; 64^3
 // (ratio 2.1) gained nothing mixed and lost 2 % in FP64, so it does not wait.
+// Position of a kernel class in the one-stream launch order (0: the workspace
+// clear that precedes it).  A batch launches its systems' kernels class by
+// class in this order.
+int batch_rank(int kind)
+{
+    static const int rank[KC_COUNT] = {
+        /* KC_BIN */ 5, /* KC_SCAN */ 6, /* KC_SCATTER */ 7, /* KC_CELLSORT */ 8,
+        /* KC_PHASE */ 1, /* KC_SK */ 2, /* KC_SKREDUCE */ 3, /* KC_GATHER */ 4,
+        /* KC_PAIRLIST */ 9, /* KC_PAIR */ 10, /* KC_FINAL_P */ 11, /* KC_FINAL_E */ 12};
+    return rank[kind];
+}
+
 bool phase_first(const ewald_params &prm, int64_t n)
 {
     const double L = prm.box_L, rc = prm.r_c, K = prm.k_max;
@@ -831,7 +858,12 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
 
     hipError_t e = hipSuccess;
     auto run = [&](hipStream_t st, int kind, auto &&fn) {
-        if (e == hipSuccess) e = allow_prof ? timed(p, st, kind, fn) : fn();
+        if (e != hipSuccess) return;
+        if (t_batch) {
+            t_batch->kind = batch_rank(kind);
+            t_batch->occ = 0;
+        }
+        e = allow_prof ? timed(p, st, kind, fn) : fn();
     };
     // Reciprocal space on the plan's own stream, from the caller's positions and
     // charges: it needs nothing from the cell list, so it runs beside the real
@@ -1103,6 +1135,124 @@ ewald_status ewald_energy_forces_noalloc(ewald_plan_t p, int64_t n, const double
     if (!p->scratch) return EWALD_ERR_DEVICE;
     // the array keeps whatever the last call on this device left in it
     return run_in_buffers(p, n, pos, q, energy, forces, dEdq, p->scratch, z);
+}
+
+ewald_status ewald_energy_forces_batch(int32_t count, const ewald_plan_t *plans, const int64_t *n,
+                                       const double *const *pos, const double *const *q, double *const *energy,
+                                       double *const *forces, double *const *dEdq, void *const *workspace,
+                                       const size_t *workspace_bytes, void *stream)
+{
+    if (count < 1 || count > EWALD_BATCH_MAX || !plans || !n || !pos || !q || !energy) return EWALD_ERR_INVALID_ARG;
+    if (!plans[0]) return EWALD_ERR_INVALID_ARG;
+    const int dev = plans[0]->device;
+    std::vector<Sizes> zs((size_t)count);
+    for (int i = 0; i < count; ++i) {
+        ewald_plan_t p = plans[i];
+        if (!p || p->device != dev || !pos[i] || !q[i] || !energy[i] || n[i] < 1) return EWALD_ERR_INVALID_ARG;
+        if (n[i] > p->prm.n_max) return EWALD_ERR_CAPACITY;
+        void *ws = workspace ? workspace[i] : nullptr;
+        if (ws) {
+            if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return EWALD_ERR_INVALID_ARG;
+            compute_sizes(p->prm, p->kl, p->nc, n[i], zs[i]);
+            if (!workspace_bytes || zs[i].work > workspace_bytes[i]) return EWALD_ERR_CAPACITY;
+        } else {
+            // the plan's own buffers serve one system of the batch at most
+            if (!p->has_work) return EWALD_ERR_INVALID_ARG;
+            for (int j = 0; j < i; ++j)
+                if (plans[j] == p && !(workspace && workspace[j])) return EWALD_ERR_INVALID_ARG;
+        }
+    }
+    DeviceGuard dg(dev);
+    if (!dg.ok()) return EWALD_ERR_DEVICE;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // 1. every system's launch sequence, recorded instead of launched
+    BatchRecorder rec;
+    {
+        struct Install {
+            explicit Install(BatchRecorder *r) { t_batch = r; }
+            ~Install() { t_batch = nullptr; }
+        } install(&rec);
+        for (int i = 0; i < count; ++i) {
+            ewald_plan_t p = plans[i];
+            rec.sys = i;
+            Work w = p->w;
+            void *ws = workspace ? workspace[i] : nullptr;
+            if (ws) {
+                carve_work(static_cast<char *>(ws), zs[i], w);
+                rec.kind = 0;
+                rec.occ = 0;
+                (void)launch_zero(s, ws, zeroed_bytes(zs[i]));
+            }
+            p->last_graph = false;
+            const ewald_status st = launch_path(p, w, s, true, n[i], pos[i], q[i], energy[i],
+                                                forces ? forces[i] : nullptr, dEdq ? dEdq[i] : nullptr, nullptr,
+                                                false, false);
+            if (st != EWALD_OK) return st;
+        }
+    }
+    // 2. one launch per (kernel class, occurrence, kernel instance, block
+    // size), in the launch order of a single evaluation: each system's
+    // launches keep their order, and the launches of one class run together
+    const std::vector<LaunchRecord> &r = rec.recs;
+    for (size_t k = 1; k < r.size(); ++k)
+        if (r[k].sys == r[k - 1].sys &&
+            (r[k].kind < r[k - 1].kind || (r[k].kind == r[k - 1].kind && r[k].occ <= r[k - 1].occ)))
+            return EWALD_ERR_DEVICE;  // not in launch order (not expected)
+    std::vector<int> order(r.size());
+    for (size_t k = 0; k < r.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return r[a].kind != r[b].kind ? r[a].kind < r[b].kind : r[a].occ < r[b].occ;
+    });
+    std::vector<unsigned char> pack;
+    hipError_t e = hipSuccess;
+    for (size_t lo = 0; lo < order.size() && e == hipSuccess;) {
+        size_t hi = lo;
+        while (hi < order.size() && r[order[hi]].kind == r[order[lo]].kind && r[order[hi]].occ == r[order[lo]].occ)
+            ++hi;
+        std::vector<bool> done(hi - lo, false);
+        for (size_t g = lo; g < hi && e == hipSuccess; ++g) {
+            if (done[g - lo]) continue;
+            const LaunchRecord &head = r[order[g]];
+            std::vector<int> members;
+            for (size_t m = g; m < hi; ++m)
+                if (!done[m - lo] && r[order[m]].many == head.many && r[order[m]].threads == head.threads) {
+                    members.push_back(order[m]);
+                    done[m - lo] = true;
+                }
+            // at most cap systems per launch
+            for (size_t c0 = 0; c0 < members.size() && e == hipSuccess; c0 += (size_t)head.cap) {
+                const size_t c1 = std::min(members.size(), c0 + (size_t)head.cap);
+                pack.assign(head.pack_size, 0);
+                BatchSpan *span = reinterpret_cast<BatchSpan *>(pack.data() + head.span_off);
+                int64_t blocks = 0;
+                size_t smem = 0;
+                for (size_t m = c0; m < c1; ++m) {
+                    const LaunchRecord &x = r[members[m]];
+                    std::memcpy(pack.data() + (m - c0) * head.args_size, rec.args.data() + x.args_off, head.args_size);
+                    span[m - c0].first = (int)blocks;
+                    span[m - c0].gx = (int)x.grid.x;
+                    blocks += (int64_t)x.grid.x * x.grid.y * x.grid.z;
+                    smem = std::max(smem, x.smem);
+                }
+                span[c1 - c0].first = (int)blocks;
+                const int nsys = (int)(c1 - c0);
+                std::memcpy(pack.data() + head.nsys_off, &nsys, sizeof(int));
+                if (blocks == 0) continue;
+                if (blocks > INT32_MAX) {
+                    e = hipErrorInvalidConfiguration;
+                    break;
+                }
+                void *argv[] = {pack.data()};
+                e = hipLaunchKernel(head.many, dim3((unsigned)blocks), dim3((unsigned)head.threads), argv, smem, s);
+            }
+        }
+        lo = hi;
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return EWALD_ERR_DEVICE;
+    }
+    return EWALD_OK;
 }
 
 ewald_status ewald_energy(ewald_plan_t p, int64_t n, const double *pos, const double *q, double *energy)

@@ -115,6 +115,12 @@ def _load():
     lib.ewald_energy_forces_ws.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_size_t]
     lib.ewald_energy_forces_noalloc.restype = ctypes.c_int
     lib.ewald_energy_forces_noalloc.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp]
+    lib.ewald_energy_forces_batch.restype = ctypes.c_int
+    lib.ewald_energy_forces_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(ctypes.c_size_t), vp]
     lib.ewald_energy.restype = ctypes.c_int
     lib.ewald_energy.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
     lib.ewald_energy_backward.restype = ctypes.c_int
@@ -386,6 +392,46 @@ class Plan:
 
     def __exit__(self, *exc):
         self.release()
+
+
+BATCH_MAX = 1024
+
+
+def energy_forces_batch(items, workspaces=None):
+    """ewald_energy_forces_batch(): many systems in one launch sequence.
+
+    ``items``: sequence of (plan, pos, q, out) with ``out`` = (energy[5],
+    forces (n,3) or None, dEdq (n,) or None) preallocated float64 device
+    tensors.  ``workspaces``: None (each plan's own buffers) or one device
+    tensor per item (or None entries) of at least
+    ``plan.eval_workspace_bytes(n)`` bytes.  Enqueued on torch's current
+    stream; returns the list of ``out``."""
+    count = len(items)
+    if not 1 <= count <= BATCH_MAX:
+        raise ValueError(f"a batch holds 1 .. {BATCH_MAX} systems")
+    vp = ctypes.c_void_p
+    plans, ns = (vp * count)(), (ctypes.c_int64 * count)()
+    pos_a, q_a, e_a, f_a, g_a, w_a = ((vp * count)() for _ in range(6))
+    wb = (ctypes.c_size_t * count)()
+    for i, (plan, pos, q, out) in enumerate(items):
+        import torch
+        n = int(q.shape[0])
+        for name, t, shape in (("pos", pos, (n, 3)), ("q", q, (n,))):
+            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        e, f, g = out
+        plans[i], ns[i] = plan.handle, n
+        pos_a[i], q_a[i], e_a[i] = pos.data_ptr(), q.data_ptr(), e.data_ptr()
+        f_a[i] = f.data_ptr() if f is not None else None
+        g_a[i] = g.data_ptr() if g is not None else None
+        w = workspaces[i] if workspaces is not None else None
+        w_a[i] = w.data_ptr() if w is not None else None
+        wb[i] = w.numel() * w.element_size() if w is not None else 0
+    st = _load().ewald_energy_forces_batch(count, plans, ns, pos_a, q_a, e_a, f_a, g_a, w_a, wb,
+                                           _stream_handle())
+    if st != OK:
+        raise EwaldError(st, "ewald_energy_forces_batch")
+    return [it[3] for it in items]
 
 
 def energy_forces(pos, q, box_L, alpha, r_c, k_max, precision="fp64", dEdq=False):

@@ -76,6 +76,15 @@ def test_null_handling():
     assert lib.ewald_plan_set_stream(None, None) == ew.ERR_INVALID_ARG
     assert lib.ewald_debug_copy_sk(None, None, None) == ew.ERR_INVALID_ARG
     assert lib.ewald_profile_enable(None, 1) == ew.ERR_INVALID_ARG
+    # batches: count outside 1 .. EWALD_BATCH_MAX, or NULL arrays and plans
+    vp = ctypes.c_void_p
+    one = (vp * 1)(None)
+    n1 = (ctypes.c_int64 * 1)(10)
+    for count in (0, -1, ew.BATCH_MAX + 1):
+        assert lib.ewald_energy_forces_batch(count, one, n1, one, one, one, None, None, None, None,
+                                             None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_energy_forces_batch(1, None, n1, one, one, one, None, None, None, None, None) == ew.ERR_INVALID_ARG
+    assert lib.ewald_energy_forces_batch(1, one, n1, one, one, one, None, None, None, None, None) == ew.ERR_INVALID_ARG
 
 
 def test_workspace_bytes_scale_with_capacity():

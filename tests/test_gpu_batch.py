@@ -1,0 +1,182 @@
+"""Batched evaluation: many independent systems in one launch sequence.
+
+ewald_energy_forces_batch() launches each kernel of the path once for all its
+systems, over a ragged work list (a system owns a contiguous range of the
+launch's workgroups).  Every system's results must equal, bit for bit, those
+of the same plan evaluated alone: the workgroups run the same code on the
+same arguments.  The batches mix precisions, sizes on both sides of the
+one-workgroup cell-list and totals kernels (512 particles), k_max on both
+structure-factor instances and on the vector-ALU fallbacks, per-system
+workspaces and plan-owned buffers, and more systems than one launch's
+argument pack holds (so a step takes several launches).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1708_01135_amd import workloads as wl
+
+from gpu_helpers import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _systems():
+    # (n, L, alpha, r_c, k_max, precision, seed)
+    out = []
+    rng = np.random.default_rng(5)
+    for i in range(12):
+        n = int(rng.integers(120, 4000))
+        L = (n / 0.08) ** (1.0 / 3.0)
+        rc = min(4.5, 0.5 * L)
+        alpha = (3.2 / rc) ** 2
+        K = int(np.ceil(np.sqrt(14.4 * alpha) * L / np.pi))
+        out.append((n, L, alpha, rc, K, "mixed" if i % 2 else "fp64", 100 + i))
+    out.append((300, 9.0, 1.0, 3.0, 30, "mixed", 200))     # second structure-factor instance
+    out.append((150, 10.0, 1.0, 3.0, 64, "fp64", 201))     # vector-ALU structure factor
+    out.append((150, 10.0, 1.0, 3.0, 90, "fp64", 202))     # and vector-ALU FP64 gather
+    out.append((240, 6.0, 1.2, 6.0, 8, "mixed", 203))      # r_c = L
+    return out
+
+
+def _inputs(systems):
+    import torch
+    dev = torch.device("cuda:0")
+    res = []
+    for (n, L, a, rc, K, prec, seed) in systems:
+        pos, q = wl.random_neutral(n, L, seed)
+        res.append((pos, q, torch.tensor(pos, device=dev), torch.tensor(q, device=dev)))
+    return res
+
+
+def _out(n):
+    import torch
+    dev = torch.device("cuda:0")
+    return (torch.empty(5, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
+            torch.empty(n, dtype=torch.float64, device=dev))
+
+
+def _np(out):
+    return tuple(t.cpu().numpy() for t in out)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("own_buffers", [False, True])
+def test_batch_bitwise_equal_to_alone(own_buffers):
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    systems = _systems()
+    inputs = _inputs(systems)
+    flags = 0 if own_buffers else ew.FLAG_NO_WORKSPACE
+    plans = [ew.Plan(s[0], s[1], s[2], s[3], s[4], s[5], flags=flags) for s in systems]
+    try:
+        # alone: one system at a time through the per-evaluation workspace path
+        alone = []
+        for p, s, (_, _, pd, qd) in zip(plans, systems, inputs):
+            ws = torch.empty(p.eval_workspace_bytes(s[0]), dtype=torch.uint8, device="cuda:0")
+            out = p.energy_forces_ws(pd, qd, ws, _out(s[0]))
+            torch.cuda.synchronize()
+            alone.append(_np(out))
+        wss = None
+        if not own_buffers:
+            wss = [torch.empty(p.eval_workspace_bytes(s[0]), dtype=torch.uint8, device="cuda:0")
+                   for p, s in zip(plans, systems)]
+        items = [(p, pd, qd, _out(s[0])) for p, s, (_, _, pd, qd) in zip(plans, systems, inputs)]
+        for rep in range(2):
+            # other device work between the batches
+            x = torch.randn(4096, device="cuda:0")
+            _ = (x * x).sum().item()
+            got = ew.energy_forces_batch(items, wss)
+            torch.cuda.synchronize()
+            for i, out in enumerate(got):
+                e, f, g = _np(out)
+                assert np.array_equal(e, alone[i][0]), (rep, i, systems[i], "energy")
+                assert np.array_equal(f, alone[i][1]), (rep, i, systems[i], "forces")
+                assert np.array_equal(g, alone[i][2]), (rep, i, systems[i], "dEdq")
+        for p in plans:
+            assert p.status() == ew.OK
+    finally:
+        for p in plans:
+            p.release()
+
+
+@pytest.mark.timeout(600)
+def test_batch_matches_oracle():
+    from paper_1708_01135_amd import ewald as ew
+    systems = [s for s in _systems() if s[0] <= 1500][:6]
+    inputs = _inputs(systems)
+    plans = [ew.Plan(s[0], s[1], s[2], s[3], s[4], s[5]) for s in systems]
+    try:
+        items = [(p, pd, qd, _out(s[0])) for p, s, (_, _, pd, qd) in zip(plans, systems, inputs)]
+        got = ew.energy_forces_batch(items)
+        for (n, L, a, rc, K, prec, seed), (pos, q, _, _), out, p in zip(systems, inputs, got, plans):
+            e, f, g = _np(out)
+            compare((e, f, g, p.status()), oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST), prec,
+                    f"batch n={n} K={K}")
+    finally:
+        for p in plans:
+            p.release()
+
+
+@pytest.mark.timeout(600)
+def test_batch_wider_than_one_launch():
+    # 40 small systems: more than one argument pack per step (the largest
+    # kernel structs hold about 28 systems), so steps split over launches
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    rng = np.random.default_rng(9)
+    systems = []
+    for i in range(40):
+        n = int(rng.integers(100, 700))
+        L = (n / 0.08) ** (1.0 / 3.0)
+        rc = min(4.5, 0.5 * L)
+        alpha = (3.2 / rc) ** 2
+        K = int(np.ceil(np.sqrt(14.4 * alpha) * L / np.pi))
+        systems.append((n, L, alpha, rc, K, "mixed", 300 + i))
+    inputs = _inputs(systems)
+    plans = [ew.Plan(s[0], s[1], s[2], s[3], s[4], s[5]) for s in systems]
+    try:
+        alone = []
+        for p, s, (_, _, pd, qd) in zip(plans, systems, inputs):
+            out = p.energy_forces(pd, qd, True, True)
+            torch.cuda.synchronize()
+            alone.append(_np(out))
+        items = [(p, pd, qd, _out(s[0])) for p, s, (_, _, pd, qd) in zip(plans, systems, inputs)]
+        got = ew.energy_forces_batch(items)
+        torch.cuda.synchronize()
+        for i, out in enumerate(got):
+            e, f, g = _np(out)
+            assert np.array_equal(e, alone[i][0]) and np.array_equal(f, alone[i][1]) and \
+                np.array_equal(g, alone[i][2]), (i, systems[i])
+    finally:
+        for p in plans:
+            p.release()
+
+
+def test_batch_rejects_bad_arguments():
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    pos, q = wl.random_neutral(200, 8.0, 1)
+    pd = torch.tensor(pos, device="cuda:0")
+    qd = torch.tensor(q, device="cuda:0")
+    with ew.Plan(200, 8.0, 1.0, 3.0, 8, "fp64") as p, \
+            ew.Plan(200, 8.0, 1.0, 3.0, 8, "fp64", flags=ew.FLAG_NO_WORKSPACE) as pn:
+        # the same plan's own buffers twice
+        with pytest.raises(ew.EwaldError) as ei:
+            ew.energy_forces_batch([(p, pd, qd, _out(200)), (p, pd, qd, _out(200))])
+        assert ei.value.status == ew.ERR_INVALID_ARG
+        # a plan without buffers and no workspace
+        with pytest.raises(ew.EwaldError) as ei:
+            ew.energy_forces_batch([(pn, pd, qd, _out(200))])
+        assert ei.value.status == ew.ERR_INVALID_ARG
+        # a workspace that is too small
+        ws = torch.empty(1024, dtype=torch.uint8, device="cuda:0")
+        with pytest.raises(ew.EwaldError) as ei:
+            ew.energy_forces_batch([(pn, pd, qd, _out(200))], [ws])
+        assert ei.value.status == ew.ERR_CAPACITY
+        # the same plan twice with workspaces of its own is fine
+        w1 = torch.empty(pn.eval_workspace_bytes(200), dtype=torch.uint8, device="cuda:0")
+        w2 = torch.empty(pn.eval_workspace_bytes(200), dtype=torch.uint8, device="cuda:0")
+        a, b = ew.energy_forces_batch([(pn, pd, qd, _out(200)), (pn, pd, qd, _out(200))], [w1, w2])
+        torch.cuda.synchronize()
+        assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b))
