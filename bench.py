@@ -349,26 +349,34 @@ def serving(n_systems, passes, express_cus=False):
            "k_range": [min(it["k_max"] for it in mix), max(it["k_max"] for it in mix)], "precision": "mixed",
            "generate_s": round(t_gen, 1)}
 
-    def saturate(srv, ids):
+    def saturate(srv, ids, sel):
         t0 = time.perf_counter()
-        tick = [srv.submit(ids[s], pos[s], q[s], out=outs[s]) for s in range(n_systems)]
+        tick = [srv.submit(ids[s], pos[s], q[s], out=outs[s]) for s in sel]
         for t in tick:
             srv.wait(t)
         return time.perf_counter() - t0
 
-    def run(srv, ids):
-        saturate(srv, ids)  # warm-up
-        return min(saturate(srv, ids) for _ in range(3))
+    def run(srv, ids, sel=range(n_systems)):
+        saturate(srv, ids, sel)  # warm-up
+        return min(saturate(srv, ids, sel) for _ in range(3))
 
+    small = [s for s in range(n_systems) if mix[s]["n"] < 5000]
     with ewald.Server(n_streams=1, precision="mixed") as srv:
         ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
         t1 = run(srv, ids)
+    # express requests one by one instead of batched: the whole mix, and its
+    # systems below 5,000 ions alone
+    with ewald.Server(n_streams=4, precision="mixed", express_cus=express_cus, batching=False) as srv:
+        ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
+        t4_nb = run(srv, ids)
+        t_small_nb = run(srv, ids, small)
     with ewald.Server(n_streams=4, precision="mixed", express_cus=express_cus) as srv:
         t_add = time.perf_counter()
         ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
         t_add = time.perf_counter() - t_add
         res["register_s"] = round(t_add, 2)
         t4 = run(srv, ids)
+        t_small = run(srv, ids, small)
         st = srv.stats()
         res["arena_gb"] = round(st["budget"] / 1e9, 2)
         res["arena_peak_gb"] = round(st["peak_used"] / 1e9, 2)
@@ -378,7 +386,14 @@ def serving(n_systems, passes, express_cus=False):
         res["express_cus"] = bool(express_cus)
         res["saturation"] = {"streams_4": {"systems_per_s": sat, "particle_evals_per_s": ns.sum() / t4,
                                            "tflops_alg": 30.0 * units / t4 / 1e12},
-                             "streams_1": {"systems_per_s": n_systems / t1, "particle_evals_per_s": ns.sum() / t1}}
+                             "streams_4_unbatched": {"systems_per_s": n_systems / t4_nb,
+                                                     "particle_evals_per_s": ns.sum() / t4_nb},
+                             "streams_1": {"systems_per_s": n_systems / t1, "particle_evals_per_s": ns.sum() / t1},
+                             "below_5000": {"systems": len(small), "systems_per_s": len(small) / t_small,
+                                            "unbatched_systems_per_s": len(small) / t_small_nb}}
+        res["batched_launches"] = st["batches"]
+        res["batched_requests"] = st["batched"]
+        res["requests_served"] = st["completed"]
         # stand-alone latency of every system: one request at a time
         alone = np.zeros(n_systems)
         for s in range(n_systems):

@@ -16,8 +16,14 @@
  *     stream, stream 0, so that it never queues behind a large one, and any
  *     other request to the stream with the least outstanding estimated work
  *     among the rest (with one stream, everything goes to it);
- *   - a stream takes at most 2 requests at a time; the rest wait in the
- *     dispatcher, where a small request that arrives later still passes them;
+ *   - a stream takes at most 2 launch sequences at a time; the rest wait in
+ *     the dispatcher, where a small request that arrives later still passes
+ *     them;
+ *   - the small requests that can start together (their workspaces fit, the
+ *     express stream has a slot) go out as one batched launch sequence
+ *     (ewald_energy_forces_batch: each kernel launched once over a ragged work
+ *     list spanning all of them), at most 64 at a time, unless the server was
+ *     made with EWALD_SERVER_FLAG_NO_BATCH;
  *   - the systems' plans run their real- and reciprocal-space chains on the
  *     request's stream (EWALD_FLAG_ONE_STREAM); requests in flight on
  *     different streams overlap instead;
@@ -27,7 +33,7 @@
  *     240, so a small request never waits for the workgroups of a large one
  *     to leave a CU (throughput of large requests drops by about the share of
  *     the reserved CUs).
- * Completion is detected by polling one event per request; the request's
+ * Completion is detected by polling one event per launch sequence; a request's
  * latency is measured on the server's monotonic clock from its submission to
  * the moment the dispatcher observes its completion.
  *
@@ -66,8 +72,10 @@ typedef struct ewald_server_s *ewald_server_t;
  *   device      HIP device ordinal.
  *   n_streams   streams requests are spread over, 1 <= n_streams <= 16.
  *   precision   EWALD_PRECISION_FP64 or EWALD_PRECISION_MIXED, for every system.
- *   flags       0, or EWALD_SERVER_FLAG_EXPRESS_CUS: the express stream gets
- *               compute units of its own (see below).
+ *   flags       0, or any of EWALD_SERVER_FLAG_EXPRESS_CUS (the express
+ *               stream gets compute units of its own, see above) and
+ *               EWALD_SERVER_FLAG_NO_BATCH (express requests go out one by
+ *               one instead of batched).
  *   hbm_budget  bytes of the device arena for the buffers of requests in
  *               flight, allocated when the server is created; 0 means 90 % of
  *               the free device memory, at most 8 GiB. */
@@ -80,6 +88,7 @@ typedef struct {
 } ewald_server_params;
 
 #define EWALD_SERVER_FLAG_EXPRESS_CUS 1
+#define EWALD_SERVER_FLAG_NO_BATCH 2
 
 /* Counters of a server (host values). */
 typedef struct {
@@ -93,6 +102,8 @@ typedef struct {
     int64_t held;          /* requests now waiting for arena memory    */
     int64_t held_total;    /* requests that had to wait for memory     */
     int64_t masked_streams; /* bulk streams created with a CU mask     */
+    int64_t batches;       /* batched launch sequences (2+ requests)  */
+    int64_t batched;       /* requests those sequences carried        */
 } ewald_server_stats;
 
 /* Create a server and start its dispatcher thread.  *out is NULL on failure.

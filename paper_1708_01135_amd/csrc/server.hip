@@ -35,6 +35,9 @@ constexpr double kMaxHoldBypass = 0.020;
 // the rest wait in the dispatcher's pending list, where a small request that
 // arrives later can still pass them (and their workspace is not yet taken).
 constexpr int kMaxInFlightPerStream = 2;
+// Express requests that can start together go out as one batched launch
+// sequence (ewald_energy_forces_batch), at most this many at a time.
+constexpr int kMaxBatch = 64;
 constexpr size_t kArenaAlign = 256;
 // With EWALD_SERVER_FLAG_EXPRESS_CUS: compute units of the express stream, two
 // on each of the 8 XCDs of a 256-CU part, bits 32 g + g and 32 g + g + 8 for
@@ -78,9 +81,16 @@ struct Request {
     double cost = 0.0;
     size_t ws_bytes = 0, ws_off = 0;  // its block of the arena
     int stream = -1;
-    hipEvent_t ev = nullptr;
     ewald_status status = EWALD_OK;
     bool done = false, waited = false, held = false;
+};
+
+// One enqueued launch sequence (one request, or a batch of express requests)
+// and the event recorded after it.
+struct Launch {
+    hipEvent_t ev = nullptr;
+    int stream = -1;
+    std::vector<Request *> reqs;
 };
 
 // First-fit allocator over one device allocation (host bookkeeping only; used
@@ -180,9 +190,11 @@ struct ewald_server_s {
     std::list<Request *> pending;  // seen, not yet enqueued (in submission order)
     int64_t pass = 0;              // start_pending passes
     int masked = 0;                // bulk streams created with the CU mask
-    std::vector<Request *> flight;
+    std::vector<Launch *> flight;
+    bool batching = true;
+    int64_t batches = 0, batched = 0;  // batched launch sequences, and the requests they carried
     std::vector<double> load;
-    std::vector<int> stream_flight;  // requests in flight per stream
+    std::vector<int> stream_flight;  // launch sequences in flight per stream
     std::vector<hipEvent_t> events;
     std::thread worker;
 };
@@ -223,53 +235,96 @@ int pick_stream(const ewald_server_s *s, const Request *r)
     return st;
 }
 
-// Enqueue one request whose workspace block is reserved on stream st.
-void enqueue(ewald_server_s *s, Request *r, int st)
+// Enqueue requests whose workspace blocks are reserved, on stream st: one
+// request alone, or several as one batched launch sequence.
+void enqueue(ewald_server_s *s, const std::vector<Request *> &rs, int st)
 {
-    System *y = r->sys;
     hipEvent_t ev = take_event(s);
     ewald_status rc = ev ? EWALD_OK : EWALD_ERR_DEVICE;
-    if (rc == EWALD_OK) rc = ewald_plan_set_stream(y->plan, s->streams[st]);
-    if (rc == EWALD_OK)
-        rc = ewald_energy_forces_ws(y->plan, r->n, r->pos, r->q, r->energy, r->forces, r->dEdq,
-                                    s->arena.base() + r->ws_off, r->ws_bytes);
-    if (rc == EWALD_OK && hipEventRecord(ev, s->streams[st]) != hipSuccess) {
+    const hipStream_t stream = s->streams[st];
+    if (rc == EWALD_OK && rs.size() == 1) {
+        Request *r = rs[0];
+        rc = ewald_plan_set_stream(r->sys->plan, stream);
+        if (rc == EWALD_OK)
+            rc = ewald_energy_forces_ws(r->sys->plan, r->n, r->pos, r->q, r->energy, r->forces, r->dEdq,
+                                        s->arena.base() + r->ws_off, r->ws_bytes);
+    } else if (rc == EWALD_OK) {
+        const size_t k = rs.size();
+        std::vector<ewald_plan_t> plans(k);
+        std::vector<int64_t> n(k);
+        std::vector<const double *> pos(k), q(k);
+        std::vector<double *> energy(k), forces(k), dEdq(k);
+        std::vector<void *> ws(k);
+        std::vector<size_t> wsb(k);
+        for (size_t i = 0; i < k; ++i) {
+            const Request *r = rs[i];
+            plans[i] = r->sys->plan;
+            n[i] = r->n;
+            pos[i] = r->pos;
+            q[i] = r->q;
+            energy[i] = r->energy;
+            forces[i] = r->forces;
+            dEdq[i] = r->dEdq;
+            ws[i] = s->arena.base() + r->ws_off;
+            wsb[i] = r->ws_bytes;
+        }
+        rc = ewald_energy_forces_batch((int32_t)k, plans.data(), n.data(), pos.data(), q.data(), energy.data(),
+                                       forces.data(), dEdq.data(), ws.data(), wsb.data(), stream);
+    }
+    if (rc == EWALD_OK && hipEventRecord(ev, stream) != hipSuccess) {
         (void)hipGetLastError();
         rc = EWALD_ERR_DEVICE;
     }
     std::lock_guard<std::mutex> lk(s->mu);
-    y->queued -= 1;
     if (rc != EWALD_OK) {
         if (ev) s->events.push_back(ev);
-        s->arena.release(r->ws_off, r->ws_bytes);
+        for (Request *r : rs) {
+            r->sys->queued -= 1;
+            s->arena.release(r->ws_off, r->ws_bytes);
+            r->status = rc;
+            r->t_done = now_s();
+            r->done = true;
+            s->completed += 1;
+        }
         s->used = s->arena.used();
-        r->status = rc;
-        r->t_done = now_s();
-        r->done = true;
-        s->completed += 1;
         s->cv_done.notify_all();
         return;
     }
-    r->ev = ev;
-    r->stream = st;
-    y->stream = st;
-    y->in_flight += 1;
-    s->in_flight += 1;
-    s->load[st] += r->cost;
+    Launch *l = new Launch();
+    l->ev = ev;
+    l->stream = st;
+    l->reqs = rs;
+    for (Request *r : rs) {
+        System *y = r->sys;
+        y->queued -= 1;
+        r->stream = st;
+        y->stream = st;
+        y->in_flight += 1;
+        s->in_flight += 1;
+        s->load[st] += r->cost;
+    }
+    if (rs.size() > 1) {
+        s->batches += 1;
+        s->batched += (int64_t)rs.size();
+    }
     s->stream_flight[st] += 1;
-    s->flight.push_back(r);
+    s->flight.push_back(l);
 }
 
 // Starts pending requests, in submission order, when their stream has a slot
 // and their workspace fits the arena.  One that does not fit is held (it stays
 // pending) and later ones may go ahead, until it has waited kMaxHoldBypass:
 // then nothing of its class (express or bulk) behind it starts before it does.
-// A system's requests start in submission order.  Returns whether any started.
+// A system's requests start in submission order.  The express requests that
+// can start in one pass go out together as one batched launch sequence (one
+// slot of the express stream), unless batching is off.  Returns whether any
+// started.
 bool start_pending(ewald_server_s *s)
 {
     bool any = false, blocked[2] = {false, false};
     const double now = now_s();
     const int64_t pass = ++s->pass;
+    std::vector<Request *> batch;
     for (auto it = s->pending.begin(); it != s->pending.end();) {
         Request *r = *it;
         const int cls = is_express(s, r) ? 0 : 1;
@@ -279,7 +334,9 @@ bool start_pending(ewald_server_s *s)
             continue;
         }
         const int st = pick_stream(s, r);
-        if (st < 0) {  // no slot now; later requests of other systems may have one
+        const bool joins = s->batching && cls == 0 && st == 0;
+        if (st < 0 || (joins && (int)batch.size() >= kMaxBatch)) {
+            // no slot now; later requests of other systems may have one
             r->sys->hold_pass = pass;
             ++it;
             continue;
@@ -294,7 +351,10 @@ bool start_pending(ewald_server_s *s)
                 s->peak_used = s->arena.peak();
             }
             it = s->pending.erase(it);
-            enqueue(s, r, st);
+            if (joins)
+                batch.push_back(r);
+            else
+                enqueue(s, {r}, st);
             any = true;
             continue;
         }
@@ -308,16 +368,17 @@ bool start_pending(ewald_server_s *s)
         if (now - r->t_submit > kMaxHoldBypass) blocked[cls] = true;
         ++it;
     }
+    if (!batch.empty()) enqueue(s, batch, 0);
     return any;
 }
 
-// Completion of requests in flight; returns whether any completed.
+// Completion of launch sequences in flight; returns whether any completed.
 bool poll_flight(ewald_server_s *s)
 {
     bool any = false;
     for (size_t i = 0; i < s->flight.size();) {
-        Request *r = s->flight[i];
-        const hipError_t e = hipEventQuery(r->ev);
+        Launch *l = s->flight[i];
+        const hipError_t e = hipEventQuery(l->ev);
         if (e == hipErrorNotReady) {
             ++i;
             continue;
@@ -326,19 +387,21 @@ bool poll_flight(ewald_server_s *s)
         if (e != hipSuccess) (void)hipGetLastError();
         {
             std::lock_guard<std::mutex> lk(s->mu);
-            s->events.push_back(r->ev);
-            r->ev = nullptr;
-            s->arena.release(r->ws_off, r->ws_bytes);
+            s->events.push_back(l->ev);
+            for (Request *r : l->reqs) {
+                s->arena.release(r->ws_off, r->ws_bytes);
+                s->load[l->stream] = std::max(0.0, s->load[l->stream] - r->cost);
+                r->t_done = t;
+                if (e != hipSuccess) r->status = EWALD_ERR_DEVICE;
+                r->done = true;
+                r->sys->in_flight -= 1;
+                s->in_flight -= 1;
+                s->completed += 1;
+            }
             s->used = s->arena.used();
-            s->load[r->stream] = std::max(0.0, s->load[r->stream] - r->cost);
-            s->stream_flight[r->stream] -= 1;
-            r->t_done = t;
-            if (e != hipSuccess) r->status = EWALD_ERR_DEVICE;
-            r->done = true;
-            r->sys->in_flight -= 1;
-            s->in_flight -= 1;
-            s->completed += 1;
+            s->stream_flight[l->stream] -= 1;
         }
+        delete l;
         s->flight[i] = s->flight.back();
         s->flight.pop_back();
         any = true;
@@ -384,7 +447,7 @@ ewald_status ewald_server_create(const ewald_server_params *params, ewald_server
     if (!out) return EWALD_ERR_INVALID_ARG;
     *out = nullptr;
     if (!params || params->n_streams < 1 || params->n_streams > kMaxStreams ||
-        (params->flags & ~EWALD_SERVER_FLAG_EXPRESS_CUS) != 0 ||
+        (params->flags & ~(EWALD_SERVER_FLAG_EXPRESS_CUS | EWALD_SERVER_FLAG_NO_BATCH)) != 0 ||
         params->device < 0 ||
         (params->precision != EWALD_PRECISION_FP64 && params->precision != EWALD_PRECISION_MIXED))
         return EWALD_ERR_INVALID_ARG;
@@ -399,6 +462,7 @@ ewald_status ewald_server_create(const ewald_server_params *params, ewald_server
     ewald_server_s *s = new (std::nothrow) ewald_server_s();
     if (!s) return EWALD_ERR_OUT_OF_MEMORY;
     s->prm = *params;
+    s->batching = (params->flags & EWALD_SERVER_FLAG_NO_BATCH) == 0;
     s->budget = params->hbm_budget;
     if (s->budget == 0) {
         size_t free_b = 0, total_b = 0;
@@ -623,6 +687,8 @@ ewald_status ewald_server_get_stats(ewald_server_t s, ewald_server_stats *out)
     out->held = s->held;
     out->held_total = s->held_total;
     out->masked_streams = s->masked;
+    out->batches = s->batches;
+    out->batched = s->batched;
     return EWALD_OK;
 }
 

@@ -32,6 +32,7 @@ FLAG_NO_GRAPH = 4
 FLAG_NO_WORKSPACE = 8
 FLAG_ONE_STREAM = 16
 SERVER_FLAG_EXPRESS_CUS = 1
+SERVER_FLAG_NO_BATCH = 2
 SCRATCH_BYTES = 64 << 20  # EWALD_SCRATCH_BYTES
 
 ENERGY_PARTS = ("total", "real", "recip", "self", "background")
@@ -59,7 +60,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("systems", ctypes.c_int64), ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
                 ("in_flight", ctypes.c_int64), ("budget", ctypes.c_uint64), ("used", ctypes.c_uint64),
                 ("peak_used", ctypes.c_uint64), ("held", ctypes.c_int64), ("held_total", ctypes.c_int64),
-                ("masked_streams", ctypes.c_int64)]
+                ("masked_streams", ctypes.c_int64), ("batches", ctypes.c_int64), ("batched", ctypes.c_int64)]
 
 
 class DebugStats(ctypes.Structure):
@@ -487,12 +488,13 @@ class Server:
     """
 
     def __init__(self, n_streams: int = 4, precision="mixed", device: int = 0, hbm_budget: int = 0,
-                 express_cus: bool = False):
+                 express_cus: bool = False, batching: bool = True):
         lib = _load()
         import torch
         self.device = torch.device("cuda", device)
         prm = ServerParams(int(device), int(n_streams), _precision_code(precision),
-                           SERVER_FLAG_EXPRESS_CUS if express_cus else 0, int(hbm_budget))
+                           (SERVER_FLAG_EXPRESS_CUS if express_cus else 0) | (0 if batching else SERVER_FLAG_NO_BATCH),
+                           int(hbm_budget))
         h = ctypes.c_void_p()
         st = lib.ewald_server_create(ctypes.byref(prm), ctypes.byref(h))
         if st != OK:

@@ -113,7 +113,7 @@ def test_plan_without_gpu_reports_device_error():
     assert st == ew.ERR_DEVICE and h.value is None
 
 
-@pytest.mark.parametrize("bad", [dict(n_streams=0), dict(n_streams=17), dict(precision=3), dict(flags=2),
+@pytest.mark.parametrize("bad", [dict(n_streams=0), dict(n_streams=17), dict(precision=3), dict(flags=4),
                                  dict(device=-1)])
 def test_server_rejects_bad_parameters_without_gpu(bad):
     kw = dict(device=0, n_streams=4, precision=ew.MIXED, flags=0, hbm_budget=0)

@@ -67,6 +67,38 @@ def test_mix_results_bitwise_equal_to_standalone(precision):
 
 
 @pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_express_requests_batched_bitwise_equal_to_standalone(precision):
+    # a burst of small requests: those that wait together for the express
+    # stream go out as batched launch sequences; every result must still equal
+    # the stand-alone plan's bit for bit, with batching on or off
+    from paper_1708_01135_amd import ewald as ew
+    mix = _mix(24, 2500, seed=8)
+    _to_dev(mix)
+    ref = [_standalone(it, precision) for it in mix]
+    for batching in (True, False):
+        with ew.Server(n_streams=4, precision=precision, batching=batching) as srv:
+            ids = [srv.add_system(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"]) for it in mix]
+            tickets = [(s, srv.submit(ids[s], mix[s]["pos_d"], mix[s]["q_d"], True, True))
+                       for rep in range(2) for s in range(len(mix))]
+            for s, t in tickets:
+                (e, f, g), _, _ = srv.wait(t)
+                assert np.array_equal(e.cpu().numpy(), ref[s][0]), (batching, s, "energy")
+                assert np.array_equal(f.cpu().numpy(), ref[s][1]), (batching, s, "forces")
+                assert np.array_equal(g.cpu().numpy(), ref[s][2]), (batching, s, "dEdq")
+            st = srv.stats()
+            print(f"batching={batching}: {st['batches']} batches carried {st['batched']} of "
+                  f"{st['completed']} requests", flush=True)
+            assert st["completed"] == 2 * len(mix) and st["in_flight"] == 0 and st["used"] == 0
+            if batching:
+                assert st["batches"] >= 1 and st["batched"] >= 2
+            else:
+                assert st["batches"] == 0
+            for i in ids:
+                assert srv.system_status(i) == ew.OK
+
+
+@pytest.mark.timeout(600)
 def test_served_fp64_matches_oracle():
     from paper_1708_01135_amd import ewald as ew
     mix = _mix(4, 3000, seed=5)
