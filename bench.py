@@ -24,8 +24,9 @@ oracle's own throughput on this host.  Beside the headline:
   (median of 3 runs where that stays short, one run for the 10^6-ion system)
   and single-threaded at the two smallest, with the CPU model;
 * ``serving``: the request server on a mix of 256 independent electrolyte
-  systems (N = 500 ... 50000, K = 9 ... 41): its saturation throughput and
-  p50/p99 latency under Poisson arrivals.
+  systems (N = 500 ... 50000, K = 9 ... 41): its saturation throughput with
+  small requests batched and one by one (and of the systems below 5,000 ions
+  alone), and p50/p99 latency under Poisson arrivals.
 """
 import argparse
 import hashlib
