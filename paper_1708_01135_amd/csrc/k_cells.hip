@@ -31,11 +31,9 @@ __device__ inline int cell_coord(double w, double L, int nc)
     return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
 }
 
-__device__ __forceinline__ void bin_body(int bx, int by, int64_t n, double L, int nc,
-                                                     const double *__restrict__ pos,
-                                                     const double *__restrict__ q,
-                                                     int *__restrict__ cell_of, int *__restrict__ counts,
-                                                     double *__restrict__ qpart, int *__restrict__ status)
+__device__ __forceinline__ void bin_body(int bx, int by, int64_t n, double L, int nc, const double *__restrict__ pos,
+                                         const double *__restrict__ q, int *__restrict__ cell_of,
+                                         int *__restrict__ counts, double *__restrict__ qpart, int *__restrict__ status)
 {
     __shared__ double s_q[kBinThreads];
     __shared__ double s_q2[kBinThreads];
@@ -87,11 +85,10 @@ struct KBin {
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
-__global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc,
-                                                     const double *__restrict__ pos,
-                                                     const double *__restrict__ q,
-                                                     int *__restrict__ cell_of, int *__restrict__ counts,
-                                                     double *__restrict__ qpart, int *__restrict__ status)
+__global__ __launch_bounds__(kBinThreads) void k_bin(int64_t n, double L, int nc, const double *__restrict__ pos,
+                                                     const double *__restrict__ q, int *__restrict__ cell_of,
+                                                     int *__restrict__ counts, double *__restrict__ qpart,
+                                                     int *__restrict__ status)
 {
     bin_body(blockIdx.x, blockIdx.y, n, L, nc, pos, q, cell_of, counts, qpart, status);
 }
@@ -146,9 +143,8 @@ __device__ inline int2 block_sum2(int a, int b, int2 *s_w)
 // reduces the per-block charge sums of the binning into scalars[0] = Q and
 // scalars[1] = sum q^2, in a fixed order (contiguous ranges, then a fixed tree).
 __device__ __forceinline__ void scan_tiles_body(int bx, int by, int ncell, int n_tiles, const int *__restrict__ counts,
-                                                             int2 *__restrict__ tile_sums,
-                                                             const double *__restrict__ qpart, int n_qblocks,
-                                                             double *__restrict__ scalars)
+                                                int2 *__restrict__ tile_sums, const double *__restrict__ qpart,
+                                                int n_qblocks, double *__restrict__ scalars)
 {
     __shared__ int2 s_w[kScanThreads / kLanes];
     __shared__ double s_a[kScanThreads];
@@ -193,7 +189,10 @@ struct KScanTiles {
     const double *qpart;
     int n_qblocks;
     double *scalars;
-    __device__ void run(int bx, int by) const { scan_tiles_body(bx, by, ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars); }
+    __device__ void run(int bx, int by) const
+    {
+        scan_tiles_body(bx, by, ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
@@ -207,7 +206,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int ncell, int n_ti
 
 hipError_t KScanTiles::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_scan_tiles), grid, dim3(threads), smem, s, ncell, n_tiles, counts, tile_sums, qpart, n_qblocks, scalars);
+    hipLaunchKernelGGL((k_scan_tiles), grid, dim3(threads), smem, s, ncell, n_tiles, counts, tile_sums, qpart,
+                       n_qblocks, scalars);
     return hipGetLastError();
 }
 
@@ -218,10 +218,9 @@ hipError_t KScanTiles::one(hipStream_t s, dim3 grid, int threads, size_t smem) c
 // at the matching item offsets as (cell, offset of the first home particle).  Counts and fill are cleared for the next
 // evaluation.  The last block writes cell_start[ncell] and the item count.
 __device__ __forceinline__ void scan_cells_body(int bx, int by, int ncell, int n_tiles, int *__restrict__ counts,
-                                                             int *__restrict__ fill,
-                                                             const int2 *__restrict__ tile_sums,
-                                                             int *__restrict__ cell_start, int *__restrict__ item_cell,
-                                                             int *__restrict__ item_off, int *__restrict__ n_items)
+                                                int *__restrict__ fill, const int2 *__restrict__ tile_sums,
+                                                int *__restrict__ cell_start, int *__restrict__ item_cell,
+                                                int *__restrict__ item_off, int *__restrict__ n_items)
 {
     __shared__ int2 s_w[kScanThreads / kLanes];
     const int t = (int)threadIdx.x, lane = t % kLanes, wave = t / kLanes;
@@ -300,28 +299,32 @@ struct KScanCells {
     int *item_cell;
     int *item_off;
     int *n_items;
-    __device__ void run(int bx, int by) const { scan_cells_body(bx, by, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items); }
+    __device__ void run(int bx, int by) const
+    {
+        scan_cells_body(bx, by, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_cells(int ncell, int n_tiles, int *__restrict__ counts,
-                                                             int *__restrict__ fill,
-                                                             const int2 *__restrict__ tile_sums,
+                                                             int *__restrict__ fill, const int2 *__restrict__ tile_sums,
                                                              int *__restrict__ cell_start, int *__restrict__ item_cell,
                                                              int *__restrict__ item_off, int *__restrict__ n_items)
 {
-    scan_cells_body(blockIdx.x, blockIdx.y, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items);
+    scan_cells_body(blockIdx.x, blockIdx.y, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off,
+                    n_items);
 }
 
 hipError_t KScanCells::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_scan_cells), grid, dim3(threads), smem, s, ncell, n_tiles, counts, fill, tile_sums, cell_start, item_cell, item_off, n_items);
+    hipLaunchKernelGGL((k_scan_cells), grid, dim3(threads), smem, s, ncell, n_tiles, counts, fill, tile_sums,
+                       cell_start, item_cell, item_off, n_items);
     return hipGetLastError();
 }
 
 __device__ __forceinline__ void scatter_body(int bx, int by, int64_t n, const int *__restrict__ cell_of,
-                                                 const int *__restrict__ cell_start, int *__restrict__ fill,
-                                                 int *__restrict__ tmp_idx)
+                                             const int *__restrict__ cell_start, int *__restrict__ fill,
+                                             int *__restrict__ tmp_idx)
 {
     const int64_t i = (int64_t)bx * 256 + threadIdx.x;
     if (i >= n) return;
@@ -405,9 +408,8 @@ __device__ inline void bitonic_sort_block(V v, int cnt)
 // Either way the order is the same, and O(cnt log^2 cnt) bounds the work of
 // a crowded cell.
 __device__ __forceinline__ void cellsort_body(int bx, int by, double L, const int *__restrict__ cell_start,
-                                                           int *__restrict__ tmp_idx, const double *__restrict__ pos,
-                                                           const double *__restrict__ q, int *__restrict__ perm,
-                                                           d4 *__restrict__ pq)
+                                              int *__restrict__ tmp_idx, const double *__restrict__ pos,
+                                              const double *__restrict__ q, int *__restrict__ perm, d4 *__restrict__ pq)
 {
     __shared__ int s_idx[kSortLds];
     const int c = bx;
@@ -517,13 +519,11 @@ __device__ inline void group_tree256(double &a, double &b, double *s_a, double *
 // One launch instead of four, which is most of a small system's real-space
 // path.
 __device__ __forceinline__ void cells_small_body(int bx, int by, int n, double L, int nc,
-                                                               const double *__restrict__ pos,
-                                                               const double *__restrict__ q,
-                                                               int *__restrict__ cell_start,
-                                                               int *__restrict__ item_cell, int *__restrict__ item_off,
-                                                               int *__restrict__ n_items, double *__restrict__ scalars,
-                                                               int *__restrict__ perm, d4 *__restrict__ pq,
-                                                               int *__restrict__ status)
+                                                 const double *__restrict__ pos, const double *__restrict__ q,
+                                                 int *__restrict__ cell_start, int *__restrict__ item_cell,
+                                                 int *__restrict__ item_off, int *__restrict__ n_items,
+                                                 double *__restrict__ scalars, int *__restrict__ perm,
+                                                 d4 *__restrict__ pq, int *__restrict__ status)
 {
     __shared__ int s_key[kSmallCellsMaxN];
     __shared__ d4 s_rec[kSmallCellsMaxN];  // wrapped position and charge
@@ -658,12 +658,14 @@ struct KCellsSmall {
     int *perm;
     d4 *pq;
     int *status;
-    __device__ void run(int bx, int by) const { cells_small_body(bx, by, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status); }
+    __device__ void run(int bx, int by) const
+    {
+        cells_small_body(bx, by, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
-__global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, int nc,
-                                                               const double *__restrict__ pos,
+__global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, int nc, const double *__restrict__ pos,
                                                                const double *__restrict__ q,
                                                                int *__restrict__ cell_start,
                                                                int *__restrict__ item_cell, int *__restrict__ item_off,
@@ -671,12 +673,14 @@ __global__ __launch_bounds__(kSmallThreads) void k_cells_small(int n, double L, 
                                                                int *__restrict__ perm, d4 *__restrict__ pq,
                                                                int *__restrict__ status)
 {
-    cells_small_body(blockIdx.x, blockIdx.y, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status);
+    cells_small_body(blockIdx.x, blockIdx.y, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm,
+                     pq, status);
 }
 
 hipError_t KCellsSmall::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_cells_small), grid, dim3(threads), smem, s, n, L, nc, pos, q, cell_start, item_cell, item_off, n_items, scalars, perm, pq, status);
+    hipLaunchKernelGGL((k_cells_small), grid, dim3(threads), smem, s, n, L, nc, pos, q, cell_start, item_cell, item_off,
+                       n_items, scalars, perm, pq, status);
     return hipGetLastError();
 }
 

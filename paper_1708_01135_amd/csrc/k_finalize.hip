@@ -63,11 +63,11 @@ __device__ inline double block_tree256(double *sh)
 }
 
 __device__ __forceinline__ void final_p_body(int bx, int by, int64_t n, double L, double alpha, int n_split,
-                                                 const d4 *__restrict__ pq, const int *__restrict__ perm,
-                                                 const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
-                                                 const double *__restrict__ scalars, const double *__restrict__ gscale,
-                                                 double *__restrict__ forces, double *__restrict__ dEdq,
-                                                 double *__restrict__ epart)
+                                             const d4 *__restrict__ pq, const int *__restrict__ perm,
+                                             const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
+                                             const double *__restrict__ scalars, const double *__restrict__ gscale,
+                                             double *__restrict__ forces, double *__restrict__ dEdq,
+                                             double *__restrict__ epart)
 {
     __shared__ double s_e[256];
     const int64_t s = (int64_t)bx * 256 + threadIdx.x;
@@ -92,7 +92,10 @@ struct KFinalP {
     double *forces;
     double *dEdq;
     double *epart;
-    __device__ void run(int bx, int by) const { final_p_body(bx, by, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart); }
+    __device__ void run(int bx, int by) const
+    {
+        final_p_body(bx, by, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
@@ -103,12 +106,14 @@ __global__ __launch_bounds__(256) void k_final_p(int64_t n, double L, double alp
                                                  double *__restrict__ forces, double *__restrict__ dEdq,
                                                  double *__restrict__ epart)
 {
-    final_p_body(blockIdx.x, blockIdx.y, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart);
+    final_p_body(blockIdx.x, blockIdx.y, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq,
+                 epart);
 }
 
 hipError_t KFinalP::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_final_p), grid, dim3(threads), smem, s, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, epart);
+    hipLaunchKernelGGL((k_final_p), grid, dim3(threads), smem, s, n, L, alpha, n_split, pq, perm, freal, gpart, scalars,
+                       gscale, forces, dEdq, epart);
     return hipGetLastError();
 }
 
@@ -159,9 +164,9 @@ __device__ inline void final_energy(int n_epart, const double *epart, int n_erec
 }
 
 __device__ __forceinline__ void final_e_body(int bx, int by, int n_epart, const double *__restrict__ epart, int n_erec,
-                                                 const double *__restrict__ erec, double L, double alpha,
-                                                 const double *__restrict__ scalars, int *__restrict__ status,
-                                                 double *__restrict__ energy)
+                                             const double *__restrict__ erec, double L, double alpha,
+                                             const double *__restrict__ scalars, int *__restrict__ status,
+                                             double *__restrict__ energy)
 {
     __shared__ double sh[256];
     final_energy(n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy, sh);
@@ -179,7 +184,10 @@ struct KFinalE {
     const double *scalars;
     int *status;
     double *energy;
-    __device__ void run(int bx, int by) const { final_e_body(bx, by, n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy); }
+    __device__ void run(int bx, int by) const
+    {
+        final_e_body(bx, by, n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
@@ -193,7 +201,8 @@ __global__ __launch_bounds__(256) void k_final_e(int n_epart, const double *__re
 
 hipError_t KFinalE::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_final_e), grid, dim3(threads), smem, s, n_epart, epart, n_erec, erec, L, alpha, scalars, status, energy);
+    hipLaunchKernelGGL((k_final_e), grid, dim3(threads), smem, s, n_epart, epart, n_erec, erec, L, alpha, scalars,
+                       status, energy);
     return hipGetLastError();
 }
 
@@ -202,13 +211,12 @@ hipError_t KFinalE::one(hipStream_t s, dim3 grid, int threads, size_t smem) cons
 // sums in the same order.
 constexpr int kSmallFinalMaxN = 512;
 __device__ __forceinline__ void final_small_body(int bx, int by, int64_t n, double L, double alpha, int n_split,
-                                                     const d4 *__restrict__ pq, const int *__restrict__ perm,
-                                                     const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
-                                                     const double *__restrict__ scalars,
-                                                     const double *__restrict__ gscale, double *__restrict__ forces,
-                                                     double *__restrict__ dEdq, int n_erec,
-                                                     const double *__restrict__ erec, int *__restrict__ status,
-                                                     double *__restrict__ energy)
+                                                 const d4 *__restrict__ pq, const int *__restrict__ perm,
+                                                 const d4 *__restrict__ freal, const d4 *__restrict__ gpart,
+                                                 const double *__restrict__ scalars, const double *__restrict__ gscale,
+                                                 double *__restrict__ forces, double *__restrict__ dEdq, int n_erec,
+                                                 const double *__restrict__ erec, int *__restrict__ status,
+                                                 double *__restrict__ energy)
 {
     __shared__ double s_e[256];
     __shared__ double s_part[kSmallFinalMaxN / 256];
@@ -244,7 +252,11 @@ struct KFinalSmall {
     const double *erec;
     int *status;
     double *energy;
-    __device__ void run(int bx, int by) const { final_small_body(bx, by, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec, erec, status, energy); }
+    __device__ void run(int bx, int by) const
+    {
+        final_small_body(bx, by, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec,
+                         erec, status, energy);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
@@ -257,12 +269,14 @@ __global__ __launch_bounds__(256) void k_final_small(int64_t n, double L, double
                                                      const double *__restrict__ erec, int *__restrict__ status,
                                                      double *__restrict__ energy)
 {
-    final_small_body(blockIdx.x, blockIdx.y, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec, erec, status, energy);
+    final_small_body(blockIdx.x, blockIdx.y, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces,
+                     dEdq, n_erec, erec, status, energy);
 }
 
 hipError_t KFinalSmall::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_final_small), grid, dim3(threads), smem, s, n, L, alpha, n_split, pq, perm, freal, gpart, scalars, gscale, forces, dEdq, n_erec, erec, status, energy);
+    hipLaunchKernelGGL((k_final_small), grid, dim3(threads), smem, s, n, L, alpha, n_split, pq, perm, freal, gpart,
+                       scalars, gscale, forces, dEdq, n_erec, erec, status, energy);
     return hipGetLastError();
 }
 
@@ -273,7 +287,8 @@ hipError_t launch_finalize_particles(hipStream_t s, const FinalArgs &a, const d4
                                      double *dEdq, double *epart)
 {
     return launch(s, dim3(ceil_div(a.n, 256)), 256, 0,
-                  KFinalP{a.n, a.L, a.alpha, a.n_split, pq, perm, freal, gpart, scalars, a.gscale, forces, dEdq, epart});
+                  KFinalP{a.n, a.L, a.alpha, a.n_split, pq, perm, freal, gpart, scalars, a.gscale, forces, dEdq,
+                          epart});
 }
 
 bool finalize_small(int64_t n) { return n <= kSmallFinalMaxN; }
@@ -292,7 +307,8 @@ hipError_t launch_finalize_energy(hipStream_t s, const FinalArgs &a, const doubl
                                   double *energy)
 {
     return launch(s, dim3(1), 256, 0,
-                  KFinalE{n_epart, epart, a.n_erec, erec_part, a.L, a.alpha, scalars, const_cast<int *>(status), energy});
+                  KFinalE{n_epart, epart, a.n_erec, erec_part, a.L, a.alpha, scalars, const_cast<int *>(status),
+                          energy});
 }
 
 }  // namespace ewk

@@ -109,10 +109,9 @@ constexpr int zs_stride(int np) { return np + 16; }
 
 template <typename R, int NP>
 __device__ __forceinline__ void gather_mfma_body(int bx, int by, int64_t n, double L, int KP, int K, int nap_max,
-                                                                  const SplitTable &split, const d4 *__restrict__ pq,
-                                                                  const c64 *__restrict__ tz,
-                                                                  const MTile *__restrict__ tiles,
-                                                                  const R *__restrict__ coef, d4 *__restrict__ gpart)
+                                                 const SplitTable &split, const d4 *__restrict__ pq,
+                                                 const c64 *__restrict__ tz, const MTile *__restrict__ tiles,
+                                                 const R *__restrict__ coef, d4 *__restrict__ gpart)
 {
     using V = typename Mfma<R>::v4;
     constexpr int NSUB = NP / 16;
@@ -368,16 +367,19 @@ struct KGatherMfma {
     const MTile *tiles;
     const R *coef;
     d4 *gpart;
-    __device__ void run(int bx, int by) const { gather_mfma_body<R, NP>(bx, by, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart); }
+    __device__ void run(int bx, int by) const
+    {
+        gather_mfma_body<R, NP>(bx, by, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
 template <typename R, int NP>
 __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, double L, int KP, int K, int nap_max,
-                                                                  SplitTable split, const d4 *__restrict__ pq,
-                                                                  const c64 *__restrict__ tz,
-                                                                  const MTile *__restrict__ tiles,
-                                                                  const R *__restrict__ coef, d4 *__restrict__ gpart)
+                                                                   SplitTable split, const d4 *__restrict__ pq,
+                                                                   const c64 *__restrict__ tz,
+                                                                   const MTile *__restrict__ tiles,
+                                                                   const R *__restrict__ coef, d4 *__restrict__ gpart)
 {
     gather_mfma_body<R, NP>(blockIdx.x, blockIdx.y, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart);
 }
@@ -385,7 +387,8 @@ __global__ __launch_bounds__(kGmWaves * kLanes) void k_gather_mfma(int64_t n, do
 template <typename R, int NP>
 hipError_t KGatherMfma<R, NP>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_gather_mfma<R, NP>), grid, dim3(threads), smem, s, n, L, KP, K, nap_max, split, pq, tz, tiles, coef, gpart);
+    hipLaunchKernelGGL((k_gather_mfma<R, NP>), grid, dim3(threads), smem, s, n, L, KP, K, nap_max, split, pq, tz, tiles,
+                       coef, gpart);
     return hipGetLastError();
 }
 

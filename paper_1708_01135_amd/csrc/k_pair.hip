@@ -204,10 +204,10 @@ __device__ inline int wrap_count(int v, int nc, int &w)
 constexpr int kStreamSeg = 2048;
 
 __device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L, double rc2, int max_items,
-                                                  const int *__restrict__ n_items,
-                                                  const int *__restrict__ item_cell, const int *__restrict__ item_off,
-                                                  const int *__restrict__ cell_start, const d4 *__restrict__ pq,
-                                                  uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
+                                               const int *__restrict__ n_items, const int *__restrict__ item_cell,
+                                               const int *__restrict__ item_off, const int *__restrict__ cell_start,
+                                               const d4 *__restrict__ pq, uint32_t *__restrict__ list,
+                                               int *__restrict__ list_cnt, int cap)
 {
     // the non-empty neighbour ranges of the home cell, in offset order: start,
     // stream position (exclusive prefix of the lengths), image-shift code and
@@ -377,22 +377,28 @@ struct KPairList {
     uint32_t *list;
     int *list_cnt;
     int cap;
-    __device__ void run(int bx, int by) const { pair_list_body(bx, by, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap); }
+    __device__ void run(int bx, int by) const
+    {
+        pair_list_body(bx, by, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt,
+                       cap);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
 __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
-                                                  const int *__restrict__ n_items,
-                                                  const int *__restrict__ item_cell, const int *__restrict__ item_off,
-                                                  const int *__restrict__ cell_start, const d4 *__restrict__ pq,
-                                                  uint32_t *__restrict__ list, int *__restrict__ list_cnt, int cap)
+                                                  const int *__restrict__ n_items, const int *__restrict__ item_cell,
+                                                  const int *__restrict__ item_off, const int *__restrict__ cell_start,
+                                                  const d4 *__restrict__ pq, uint32_t *__restrict__ list,
+                                                  int *__restrict__ list_cnt, int cap)
 {
-    pair_list_body(blockIdx.x, blockIdx.y, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    pair_list_body(blockIdx.x, blockIdx.y, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list,
+                   list_cnt, cap);
 }
 
 hipError_t KPairList::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_pair_list), grid, dim3(threads), smem, s, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    hipLaunchKernelGGL((k_pair_list), grid, dim3(threads), smem, s, nc, L, rc2, max_items, n_items, item_cell, item_off,
+                       cell_start, pq, list, list_cnt, cap);
     return hipGetLastError();
 }
 
@@ -400,9 +406,9 @@ hipError_t KPairList::one(hipStream_t s, dim3 grid, int threads, size_t smem) co
 // carry global indices and image-shift codes, so no per-cell table is needed).
 template <bool MIXED, bool FIT64>
 __device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, double L, double rc2, double alpha,
-                                             const int *__restrict__ cell_start, const d4 *__restrict__ pq,
-                                             const uint32_t *__restrict__ list, const int *__restrict__ list_cnt,
-                                             int cap, d4 *__restrict__ freal)
+                                          const int *__restrict__ cell_start, const d4 *__restrict__ pq,
+                                          const uint32_t *__restrict__ list, const int *__restrict__ list_cnt, int cap,
+                                          d4 *__restrict__ freal)
 {
     constexpr int kSub = kLanes / kPairHome;  // lanes per home particle
     __shared__ double s_sh[kStencil][3];
@@ -521,7 +527,10 @@ struct KPair {
     const int *list_cnt;
     int cap;
     d4 *freal;
-    __device__ void run(int bx, int by) const { pair_body<MIXED, FIT64>(bx, by, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal); }
+    __device__ void run(int bx, int by) const
+    {
+        pair_body<MIXED, FIT64>(bx, by, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
@@ -537,7 +546,8 @@ __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double
 template <bool MIXED, bool FIT64>
 hipError_t KPair<MIXED, FIT64>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_pair<MIXED, FIT64>), grid, dim3(threads), smem, s, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
+    hipLaunchKernelGGL((k_pair<MIXED, FIT64>), grid, dim3(threads), smem, s, n, nc, L, rc2, alpha, cell_start, pq, list,
+                       list_cnt, cap, freal);
     return hipGetLastError();
 }
 

@@ -55,10 +55,10 @@ __device__ inline typename Cplx<R>::type make_c(double re, double im)
 // threads on consecutive entries.
 template <typename R>
 __device__ __forceinline__ void phase_body(int bx, int by, int64_t n, double L, int KP, const double *__restrict__ pos,
-                                                          const double *__restrict__ qv, d4 *__restrict__ pr,
-                                                          typename Cplx<R>::type *__restrict__ tx,
-                                                          typename Cplx<R>::type *__restrict__ ty,
-                                                          typename Cplx<R>::type *__restrict__ tz)
+                                           const double *__restrict__ qv, d4 *__restrict__ pr,
+                                           typename Cplx<R>::type *__restrict__ tx,
+                                           typename Cplx<R>::type *__restrict__ ty,
+                                           typename Cplx<R>::type *__restrict__ tz)
 {
     using C = typename Cplx<R>::type;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -198,13 +198,11 @@ __device__ inline void sk_fma(const c64 (&z)[kQ], const c64 &a, const c64 &b, do
 
 
 __device__ __forceinline__ void sk_body(int bx, int by, int64_t n, int chunk_len, int ts, int KP, int K1,
-                                                         const c64 *__restrict__ tx, const c64 *__restrict__ ty,
-                                                         const c64 *__restrict__ tz,
-                                                         const int *__restrict__ unit_group,
-                                                         const int *__restrict__ unit_seg,
-                                                         const int *__restrict__ row_nx,
-                                                         const int *__restrict__ row_ny, int n_rows, int n_units,
-                                                         int n_chunks, d4 *__restrict__ part)
+                                        const c64 *__restrict__ tx, const c64 *__restrict__ ty,
+                                        const c64 *__restrict__ tz, const int *__restrict__ unit_group,
+                                        const int *__restrict__ unit_seg, const int *__restrict__ row_nx,
+                                        const int *__restrict__ row_ny, int n_rows, int n_units, int n_chunks,
+                                        d4 *__restrict__ part)
 {
     extern __shared__ __align__(32) unsigned char smem[];
     const int lane = threadIdx.x & (kLanes - 1);
@@ -360,25 +358,29 @@ struct KSk {
     int n_units;
     int n_chunks;
     d4 *part;
-    __device__ void run(int bx, int by) const { sk_body(bx, by, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units, n_chunks, part); }
+    __device__ void run(int bx, int by) const
+    {
+        sk_body(bx, by, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units,
+                n_chunks, part);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
 __global__ __launch_bounds__(kSkWaves *kLanes) void k_sk(int64_t n, int chunk_len, int ts, int KP, int K1,
                                                          const c64 *__restrict__ tx, const c64 *__restrict__ ty,
-                                                         const c64 *__restrict__ tz,
-                                                         const int *__restrict__ unit_group,
+                                                         const c64 *__restrict__ tz, const int *__restrict__ unit_group,
                                                          const int *__restrict__ unit_seg,
-                                                         const int *__restrict__ row_nx,
-                                                         const int *__restrict__ row_ny, int n_rows, int n_units,
-                                                         int n_chunks, d4 *__restrict__ part)
+                                                         const int *__restrict__ row_nx, const int *__restrict__ row_ny,
+                                                         int n_rows, int n_units, int n_chunks, d4 *__restrict__ part)
 {
-    sk_body(blockIdx.x, blockIdx.y, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units, n_chunks, part);
+    sk_body(blockIdx.x, blockIdx.y, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows,
+            n_units, n_chunks, part);
 }
 
 hipError_t KSk::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_sk), grid, dim3(threads), smem, s, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg, row_nx, row_ny, n_rows, n_units, n_chunks, part);
+    hipLaunchKernelGGL((k_sk), grid, dim3(threads), smem, s, n, chunk_len, ts, KP, K1, tx, ty, tz, unit_group, unit_seg,
+                       row_nx, row_ny, n_rows, n_units, n_chunks, part);
     return hipGetLastError();
 }
 
@@ -386,14 +388,13 @@ hipError_t KSk::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 constexpr int kRedLanes = kRedSlotLanes;  // lanes cooperating on one slot
 
 template <typename R>
-__device__ __forceinline__ void sk_reduce_body(int bx, int by, int n_chunks, int n_units, int n_rows, const d4 *__restrict__ part,
-                                                   const int *__restrict__ unit_group,
-                                                   const int *__restrict__ unit_seg, const int *__restrict__ row_nx,
-                                                   const int *__restrict__ row_ny, const int *__restrict__ row_m,
-                                                   const int *__restrict__ row_item, const double *__restrict__ ck,
-                                                   d4 *__restrict__ sk, R *__restrict__ rec,
-                                                   R *__restrict__ mcoef, const int *__restrict__ row_mbase,
-                                                   double *__restrict__ erec_part)
+__device__ __forceinline__ void sk_reduce_body(int bx, int by, int n_chunks, int n_units, int n_rows,
+                                               const d4 *__restrict__ part, const int *__restrict__ unit_group,
+                                               const int *__restrict__ unit_seg, const int *__restrict__ row_nx,
+                                               const int *__restrict__ row_ny, const int *__restrict__ row_m,
+                                               const int *__restrict__ row_item, const double *__restrict__ ck,
+                                               d4 *__restrict__ sk, R *__restrict__ rec, R *__restrict__ mcoef,
+                                               const int *__restrict__ row_mbase, double *__restrict__ erec_part)
 {
     __shared__ double s_e[256];
     const int n_slots = n_units * kQ * kLanes;
@@ -512,27 +513,32 @@ struct KSkReduce {
     R *mcoef;
     const int *row_mbase;
     double *erec_part;
-    __device__ void run(int bx, int by) const { sk_reduce_body<R>(bx, by, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part); }
+    __device__ void run(int bx, int by) const
+    {
+        sk_reduce_body<R>(bx, by, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m,
+                          row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
 template <typename R>
 __global__ __launch_bounds__(256) void k_sk_reduce(int n_chunks, int n_units, int n_rows, const d4 *__restrict__ part,
-                                                   const int *__restrict__ unit_group,
-                                                   const int *__restrict__ unit_seg, const int *__restrict__ row_nx,
-                                                   const int *__restrict__ row_ny, const int *__restrict__ row_m,
-                                                   const int *__restrict__ row_item, const double *__restrict__ ck,
-                                                   d4 *__restrict__ sk, R *__restrict__ rec,
-                                                   R *__restrict__ mcoef, const int *__restrict__ row_mbase,
-                                                   double *__restrict__ erec_part)
+                                                   const int *__restrict__ unit_group, const int *__restrict__ unit_seg,
+                                                   const int *__restrict__ row_nx, const int *__restrict__ row_ny,
+                                                   const int *__restrict__ row_m, const int *__restrict__ row_item,
+                                                   const double *__restrict__ ck, d4 *__restrict__ sk,
+                                                   R *__restrict__ rec, R *__restrict__ mcoef,
+                                                   const int *__restrict__ row_mbase, double *__restrict__ erec_part)
 {
-    sk_reduce_body<R>(blockIdx.x, blockIdx.y, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
+    sk_reduce_body<R>(blockIdx.x, blockIdx.y, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny,
+                      row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
 }
 
 template <typename R>
 hipError_t KSkReduce<R>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_sk_reduce<R>), grid, dim3(threads), smem, s, n_chunks, n_units, n_rows, part, unit_group, unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
+    hipLaunchKernelGGL((k_sk_reduce<R>), grid, dim3(threads), smem, s, n_chunks, n_units, n_rows, part, unit_group,
+                       unit_seg, row_nx, row_ny, row_m, row_item, ck, sk, rec, mcoef, row_mbase, erec_part);
     return hipGetLastError();
 }
 
@@ -578,9 +584,9 @@ __device__ inline void gather_fma(const R (&v)[16], const typename Cplx<R>::type
 
 template <typename R>
 __device__ __forceinline__ void gather_body(int bx, int by, int64_t n, double L, int KP, const SplitTable &split,
-                                                const d4 *__restrict__ pq, const c64 *__restrict__ tz,
-                                                const int *__restrict__ item_meta, const R *__restrict__ rec,
-                                                d4 *__restrict__ gpart)
+                                            const d4 *__restrict__ pq, const c64 *__restrict__ tz,
+                                            const int *__restrict__ item_meta, const R *__restrict__ rec,
+                                            d4 *__restrict__ gpart)
 {
     using C = typename Cplx<R>::type;
     const int64_t j = (int64_t)bx * 256 + threadIdx.x;
@@ -671,7 +677,10 @@ struct KGather {
     const int *item_meta;
     const R *rec;
     d4 *gpart;
-    __device__ void run(int bx, int by) const { gather_body<R>(bx, by, n, L, KP, split, pq, tz, item_meta, rec, gpart); }
+    __device__ void run(int bx, int by) const
+    {
+        gather_body<R>(bx, by, n, L, KP, split, pq, tz, item_meta, rec, gpart);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 

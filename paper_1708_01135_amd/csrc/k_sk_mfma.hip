@@ -88,14 +88,11 @@ __device__ __forceinline__ void sk_tile_dispatch(int nap, const c64 *__restrict_
 // the SIMD's registers to the real-space kernels that run beside it.
 template <int NMAX>
 __device__ __forceinline__ void sk_mfma_body(int bx, int by, int64_t n, int KP, int P, int n_rows, int n_rblocks,
-                                                              int n_chunks, int chunk_len, const c64 *__restrict__ tx,
-                                                              const c64 *__restrict__ ty, const c64 *__restrict__ tz,
-                                                              const int *__restrict__ row_nx,
-                                                              const int *__restrict__ row_ny,
-                                                              const int *__restrict__ row_m,
-                                                              const int *__restrict__ unit_base,
-                                                              const int *__restrict__ tile_of, int n_slots,
-                                                              d4 *__restrict__ part)
+                                             int n_chunks, int chunk_len, const c64 *__restrict__ tx,
+                                             const c64 *__restrict__ ty, const c64 *__restrict__ tz,
+                                             const int *__restrict__ row_nx, const int *__restrict__ row_ny,
+                                             const int *__restrict__ row_m, const int *__restrict__ unit_base,
+                                             const int *__restrict__ tile_of, int n_slots, d4 *__restrict__ part)
 {
     extern __shared__ __align__(16) unsigned char smem[];  // two buffers of [3][P][KP]: q x^n, y^n, z^n
     const int nb = n_rblocks * n_chunks;
@@ -211,28 +208,35 @@ struct KSkMfma {
     const int *tile_of;
     int n_slots;
     d4 *part;
-    __device__ void run(int bx, int by) const { sk_mfma_body<NMAX>(bx, by, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part); }
+    __device__ void run(int bx, int by) const
+    {
+        sk_mfma_body<NMAX>(bx, by, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m,
+                           unit_base, tile_of, n_slots, part);
+    }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
 template <int NMAX>
 __global__ __launch_bounds__(kSmWaves *kLanes, 2) void k_sk_mfma(int64_t n, int KP, int P, int n_rows, int n_rblocks,
-                                                              int n_chunks, int chunk_len, const c64 *__restrict__ tx,
-                                                              const c64 *__restrict__ ty, const c64 *__restrict__ tz,
-                                                              const int *__restrict__ row_nx,
-                                                              const int *__restrict__ row_ny,
-                                                              const int *__restrict__ row_m,
-                                                              const int *__restrict__ unit_base,
-                                                              const int *__restrict__ tile_of, int n_slots,
-                                                              d4 *__restrict__ part)
+                                                                 int n_chunks, int chunk_len,
+                                                                 const c64 *__restrict__ tx, const c64 *__restrict__ ty,
+                                                                 const c64 *__restrict__ tz,
+                                                                 const int *__restrict__ row_nx,
+                                                                 const int *__restrict__ row_ny,
+                                                                 const int *__restrict__ row_m,
+                                                                 const int *__restrict__ unit_base,
+                                                                 const int *__restrict__ tile_of, int n_slots,
+                                                                 d4 *__restrict__ part)
 {
-    sk_mfma_body<NMAX>(blockIdx.x, blockIdx.y, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part);
+    sk_mfma_body<NMAX>(blockIdx.x, blockIdx.y, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx,
+                       row_ny, row_m, unit_base, tile_of, n_slots, part);
 }
 
 template <int NMAX>
 hipError_t KSkMfma<NMAX>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_sk_mfma<NMAX>), grid, dim3(threads), smem, s, n, KP, P, n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part);
+    hipLaunchKernelGGL((k_sk_mfma<NMAX>), grid, dim3(threads), smem, s, n, KP, P, n_rows, n_rblocks, n_chunks,
+                       chunk_len, tx, ty, tz, row_nx, row_ny, row_m, unit_base, tile_of, n_slots, part);
     return hipGetLastError();
 }
 
