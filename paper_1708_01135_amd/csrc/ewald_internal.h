@@ -210,6 +210,15 @@ constexpr int kPairReach = 2;
 constexpr int kPairHome = 8;
 constexpr int kPairIndexBits = 25;
 constexpr int64_t kPairMaxN = (int64_t)1 << kPairIndexBits;  // largest n_max the lists can index
+// Small systems, whose work items would leave the chip mostly idle, spread
+// each item's home particles over up to kPairHome waves in the list pass
+// (pair_list_split: the smallest power of two that gives kPairSmallWaves
+// waves), and give each particle a whole wave in the evaluation pass when
+// fewer than kPairSmallWaves / 2 waves of kPairHome particles would run
+// (pair_small).  Lists are the same either way.
+constexpr int kPairSmallWaves = 2048;
+int pair_list_split(int max_items);
+bool pair_small(int64_t n);
 hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, const int *n_items,
                             const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
                             uint32_t *list, int *list_cnt, int cap);

@@ -19,6 +19,9 @@
 //  2. k_pair: 8 lanes per home particle walk its list (lane s takes entries
 //     s, s+8, ...), so erfc/exp run only for pairs inside r_c; the 8 partial
 //     sums are combined by a fixed xor-shuffle tree.
+// Small systems, with too few work items to fill the chip, split an item's
+// homes over up to 8 list waves and give each particle a whole wave (64
+// lanes) in the evaluation pass.
 // Both passes run in a fixed order, so results are bitwise reproducible.  A home
 // particle whose list would overflow is evaluated by the exact direct loop
 // instead.
@@ -203,6 +206,11 @@ __device__ inline int wrap_count(int v, int nc, int &w)
 // further kStreamSeg candidates of a larger neighbourhood).
 constexpr int kStreamSeg = 2048;
 
+// SPLIT waves share a work item's kPairHome home particles (kPairHome / SPLIT
+// each): small systems, whose items are too few to fill the chip, trade
+// streaming the candidates SPLIT times for SPLIT times the waves.  A home
+// particle's list does not depend on which wave builds it.
+template <int SPLIT>
 __device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L, double rc2, int max_items,
                                                const int *__restrict__ n_items, const int *__restrict__ item_cell,
                                                const int *__restrict__ item_off, const int *__restrict__ cell_start,
@@ -217,18 +225,22 @@ __device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L,
     __shared__ uint64_t s_bits[kStreamSeg / 64];
     // neighbouring cells share one XCD's L2: remap over the actual item count
     // (known on the device only), so that padding blocks do not pile up on one XCD
+    constexpr int HPW = kPairHome / SPLIT;  // home particles of this wave
     const int nit = *n_items;
-    const int per = (nit + kXcds - 1) / kXcds;
+    const int nwork = nit * SPLIT;
+    const int per = (nwork + kXcds - 1) / kXcds;
     if ((int)bx >= per * kXcds) return;
-    const int it = xcd_remap(bx, nit);
-    if (it >= nit) return;
+    const int wk = xcd_remap(bx, nwork);
+    if (wk >= nwork) return;
+    const int it = wk / SPLIT, part = wk % SPLIT;
     (void)max_items;
     const int lane = (int)threadIdx.x;
     const int c = item_cell[it];
     const int cx = c / (nc * nc), cy = (c / nc) % nc, cz = c % nc;
     const int end = cell_start[c + 1];
-    const int i0 = cell_start[c] + item_off[it];
-    const int nh = (end - i0) < kPairHome ? (end - i0) : kPairHome;  // wave-uniform
+    const int i0 = cell_start[c] + item_off[it] + part * HPW;
+    if (i0 >= end) return;  // the item has no home particles for this wave
+    const int nh = (end - i0) < HPW ? (end - i0) : HPW;  // wave-uniform
     // lane l takes offsets l and l + 64
     int st[2], len[2], code[2], wxyz[2][3];
 #pragma unroll
@@ -282,10 +294,10 @@ __device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L,
     // ordinal of the home cell's own range without shift (never empty: it
     // holds the home particles)
     const int self_ord = __builtin_amdgcn_readlane(ordv[kCenter / kLanes], kCenter % kLanes);
-    double hx[kPairHome], hy[kPairHome], hz[kPairHome];
-    int cnt[kPairHome];
+    double hx[HPW], hy[HPW], hz[HPW];
+    int cnt[HPW];
 #pragma unroll
-    for (int h = 0; h < kPairHome; ++h) {
+    for (int h = 0; h < HPW; ++h) {
         const d4 p = pq[i0 + (h < nh ? h : 0)];
         hx[h] = p.a;
         hy[h] = p.b;
@@ -331,7 +343,7 @@ __device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L,
             const uint32_t entry = (uint32_t)j | ((uint32_t)s_code[k] << kPairIndexBits);
             const int self = k == self_ord ? j : -1;  // the home cell without shift
 #pragma unroll
-            for (int h = 0; h < kPairHome; ++h) {
+            for (int h = 0; h < HPW; ++h) {
                 if (h < nh) {
                     const double dx = hx[h] - px, dy = hy[h] - py, dz = hz[h] - pz;
                     const double r2 = dx * dx + dy * dy + dz * dz;
@@ -356,12 +368,13 @@ __device__ __forceinline__ void pair_list_body(int bx, int by, int nc, double L,
     if (lane < nh) {
         int v = 0;
 #pragma unroll
-        for (int h = 0; h < kPairHome; ++h)
+        for (int h = 0; h < HPW; ++h)
             if (h == lane) v = cnt[h];
         list_cnt[i0 + lane] = v > cap ? -1 : v;
     }
 }
 
+template <int SPLIT>
 struct KPairList {
     static constexpr int kThreads = 64;
     static constexpr int kWavesPerEu = 1;
@@ -379,38 +392,43 @@ struct KPairList {
     int cap;
     __device__ void run(int bx, int by) const
     {
-        pair_list_body(bx, by, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt,
-                       cap);
+        pair_list_body<SPLIT>(bx, by, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list,
+                              list_cnt, cap);
     }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
+template <int SPLIT>
 __global__ __launch_bounds__(64) void k_pair_list(int nc, double L, double rc2, int max_items,
                                                   const int *__restrict__ n_items, const int *__restrict__ item_cell,
                                                   const int *__restrict__ item_off, const int *__restrict__ cell_start,
                                                   const d4 *__restrict__ pq, uint32_t *__restrict__ list,
                                                   int *__restrict__ list_cnt, int cap)
 {
-    pair_list_body(blockIdx.x, blockIdx.y, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list,
-                   list_cnt, cap);
+    pair_list_body<SPLIT>(blockIdx.x, blockIdx.y, nc, L, rc2, max_items, n_items, item_cell, item_off, cell_start, pq,
+                          list, list_cnt, cap);
 }
 
-hipError_t KPairList::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+template <int SPLIT>
+hipError_t KPairList<SPLIT>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_pair_list), grid, dim3(threads), smem, s, nc, L, rc2, max_items, n_items, item_cell, item_off,
+    hipLaunchKernelGGL((k_pair_list<SPLIT>), grid, dim3(threads), smem, s, nc, L, rc2, max_items, n_items, item_cell, item_off,
                        cell_start, pq, list, list_cnt, cap);
     return hipGetLastError();
 }
 
-// Evaluation pass: a work item is any kPairHome consecutive particles (lists
-// carry global indices and image-shift codes, so no per-cell table is needed).
-template <bool MIXED, bool FIT64>
+// Evaluation pass: a work item is any HPW consecutive particles (lists carry
+// global indices and image-shift codes, so no per-cell table is needed), each
+// walked by 64 / HPW lanes: HPW = kPairHome, or 1 for small systems, whose
+// items are too few to fill the chip (the lanes of a particle, and so its
+// sums, then differ; the choice depends on n alone).
+template <bool MIXED, bool FIT64, int HPW>
 __device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, double L, double rc2, double alpha,
                                           const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                           const uint32_t *__restrict__ list, const int *__restrict__ list_cnt, int cap,
                                           d4 *__restrict__ freal)
 {
-    constexpr int kSub = kLanes / kPairHome;  // lanes per home particle
+    constexpr int kSub = kLanes / HPW;  // lanes per home particle
     __shared__ double s_sh[kStencil][3];
     const PairConsts k = pair_consts(alpha);
     const int lane = (int)threadIdx.x;
@@ -421,8 +439,8 @@ __device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, dou
     }
     __syncthreads();
     const int h = lane / kSub, s = lane % kSub;
-    const int blocks = (int)((n + kPairHome - 1) / kPairHome);
-    const int64_t i = (int64_t)xcd_remap(bx, blocks) * kPairHome + h;
+    const int blocks = (int)((n + HPW - 1) / HPW);
+    const int64_t i = (int64_t)xcd_remap(bx, blocks) * HPW + h;
     const bool act = i < n;
     const d4 me = pq[act ? i : 0];
     const int cnt = act ? list_cnt[i] : 0;
@@ -512,7 +530,7 @@ __device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, dou
     }
 }
 
-template <bool MIXED, bool FIT64>
+template <bool MIXED, bool FIT64, int HPW>
 struct KPair {
     static constexpr int kThreads = 64;
     static constexpr int kWavesPerEu = 1;
@@ -529,26 +547,69 @@ struct KPair {
     d4 *freal;
     __device__ void run(int bx, int by) const
     {
-        pair_body<MIXED, FIT64>(bx, by, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
+        pair_body<MIXED, FIT64, HPW>(bx, by, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
     }
     hipError_t one(hipStream_t s, dim3 grid, int threads, size_t smem) const;
 };
 
-template <bool MIXED, bool FIT64>
+template <bool MIXED, bool FIT64, int HPW>
 __global__ __launch_bounds__(64) void k_pair(int64_t n, int nc, double L, double rc2, double alpha,
                                              const int *__restrict__ cell_start, const d4 *__restrict__ pq,
                                              const uint32_t *__restrict__ list, const int *__restrict__ list_cnt,
                                              int cap, d4 *__restrict__ freal)
 {
-    pair_body<MIXED, FIT64>(blockIdx.x, blockIdx.y, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap, freal);
+    pair_body<MIXED, FIT64, HPW>(blockIdx.x, blockIdx.y, n, nc, L, rc2, alpha, cell_start, pq, list, list_cnt, cap,
+                                 freal);
 }
 
-template <bool MIXED, bool FIT64>
-hipError_t KPair<MIXED, FIT64>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
+template <bool MIXED, bool FIT64, int HPW>
+hipError_t KPair<MIXED, FIT64, HPW>::one(hipStream_t s, dim3 grid, int threads, size_t smem) const
 {
-    hipLaunchKernelGGL((k_pair<MIXED, FIT64>), grid, dim3(threads), smem, s, n, nc, L, rc2, alpha, cell_start, pq, list,
+    hipLaunchKernelGGL((k_pair<MIXED, FIT64, HPW>), grid, dim3(threads), smem, s, n, nc, L, rc2, alpha, cell_start, pq, list,
                        list_cnt, cap, freal);
     return hipGetLastError();
+}
+
+}  // namespace
+
+int pair_list_split(int max_items)
+{
+    int split = 1;
+    while (split < kPairHome && (int64_t)max_items * split < kPairSmallWaves) split *= 2;
+    return split;
+}
+
+bool pair_small(int64_t n) { return ceil_div(n, kPairHome) < kPairSmallWaves / 2; }
+
+namespace {
+
+template <int SPLIT>
+hipError_t launch_list(hipStream_t s, const PairArgs &a, int max_items, const int *n_items, const int *item_cell,
+                       const int *item_off, const int *cell_start, const d4 *pq, uint32_t *list, int *list_cnt, int cap)
+{
+    return launch(s, dim3(xcd_grid(max_items * SPLIT)), 64, 0,
+                  KPairList<SPLIT>{a.nc, a.L, a.rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list,
+                                   list_cnt, cap});
+}
+
+template <int HPW>
+hipError_t launch_eval(hipStream_t s, const PairArgs &a, bool mixed, const int *cell_start, const d4 *pq,
+                       const uint32_t *list, const int *list_cnt, int cap, d4 *freal)
+{
+    const int blocks = xcd_grid(ceil_div(a.n, HPW));
+    // the FP64 erfcx polynomial covers sqrt(alpha) r <= kErfcx64XMax
+    const bool fit64 = sqrt(a.alpha * a.rc2) <= kErfcx64XMax;
+    if (mixed)
+        return launch(s, dim3(blocks), 64, 0,
+                      KPair<true, false, HPW>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap,
+                                              freal});
+    if (fit64)
+        return launch(s, dim3(blocks), 64, 0,
+                      KPair<false, true, HPW>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap,
+                                              freal});
+    return launch(s, dim3(blocks), 64, 0,
+                  KPair<false, false, HPW>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap,
+                                           freal});
 }
 
 }  // namespace
@@ -557,25 +618,20 @@ hipError_t launch_pair_list(hipStream_t s, const PairArgs &a, int max_items, con
                             const int *item_cell, const int *item_off, const int *cell_start, const d4 *pq,
                             uint32_t *list, int *list_cnt, int cap)
 {
-    return launch(s, dim3(xcd_grid(max_items)), 64, 0,
-                  KPairList{a.nc, a.L, a.rc2, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt,
-                            cap});
+    switch (pair_list_split(max_items)) {
+    case 1: return launch_list<1>(s, a, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    case 2: return launch_list<2>(s, a, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    case 4: return launch_list<4>(s, a, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    default:
+        return launch_list<8>(s, a, max_items, n_items, item_cell, item_off, cell_start, pq, list, list_cnt, cap);
+    }
 }
 
 hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *cell_start, const d4 *pq,
                        const uint32_t *list, const int *list_cnt, int cap, d4 *freal)
 {
-    const int blocks = xcd_grid(ceil_div(a.n, kPairHome));
-    // the FP64 erfcx polynomial covers sqrt(alpha) r <= kErfcx64XMax
-    const bool fit64 = sqrt(a.alpha * a.rc2) <= kErfcx64XMax;
-    if (mixed)
-        return launch(s, dim3(blocks), 64, 0,
-                      KPair<true, false>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap, freal});
-    if (fit64)
-        return launch(s, dim3(blocks), 64, 0,
-                      KPair<false, true>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap, freal});
-    return launch(s, dim3(blocks), 64, 0,
-                  KPair<false, false>{a.n, a.nc, a.L, a.rc2, a.alpha, cell_start, pq, list, list_cnt, cap, freal});
+    if (pair_small(a.n)) return launch_eval<1>(s, a, mixed, cell_start, pq, list, list_cnt, cap, freal);
+    return launch_eval<kPairHome>(s, a, mixed, cell_start, pq, list, list_cnt, cap, freal);
 }
 
 }  // namespace ewk
