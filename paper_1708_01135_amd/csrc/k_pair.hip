@@ -16,9 +16,10 @@
 //     map of the range starts); the 8 home particles are wave-uniform.  For each home particle the in-range lanes are compacted
 //     with a ballot and appended, in lane order, to that particle's list of
 //     32-bit entries (sorted index | image-shift code << 25).
-//  2. k_pair: 8 lanes per home particle walk its list (lane s takes entries
-//     s, s+8, ...), so erfc/exp run only for pairs inside r_c; the 8 partial
-//     sums are combined by a fixed xor-shuffle tree.
+//  2. k_pair: 8 lanes per home particle (16 in mixed precision) walk its list
+//     (lane s takes entries s, s+8, ...), so erfc/exp run only for pairs
+//     inside r_c; the lanes' partial sums are combined by a fixed xor-shuffle
+//     tree.
 // Small systems, with too few work items to fill the chip, split an item's
 // homes over up to 8 list waves and give each particle a whole wave (64
 // lanes) in the evaluation pass.
@@ -419,9 +420,10 @@ hipError_t KPairList<SPLIT>::one(hipStream_t s, dim3 grid, int threads, size_t s
 
 // Evaluation pass: a work item is any HPW consecutive particles (lists carry
 // global indices and image-shift codes, so no per-cell table is needed), each
-// walked by 64 / HPW lanes: HPW = kPairHome, or 1 for small systems, whose
-// items are too few to fill the chip (the lanes of a particle, and so its
-// sums, then differ; the choice depends on n alone).
+// walked by 64 / HPW lanes: HPW = kPairHome (FP64), kPairHome / 2 (mixed), or 1
+// for small systems, whose items are too few to fill the chip (the lanes of a
+// particle, and so its sums, then differ; the choice depends on the precision
+// and n alone).
 template <bool MIXED, bool FIT64, int HPW>
 __device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, double L, double rc2, double alpha,
                                           const int *__restrict__ cell_start, const d4 *__restrict__ pq,
@@ -631,6 +633,10 @@ hipError_t launch_pair(hipStream_t s, const PairArgs &a, bool mixed, const int *
                        const uint32_t *list, const int *list_cnt, int cap, d4 *freal)
 {
     if (pair_small(a.n)) return launch_eval<1>(s, a, mixed, cell_start, pq, list, list_cnt, cap, freal);
+    // the mixed kernel (70 VGPRs) takes twice the waves of kPairHome particles
+    // each, to hide its load latency: 0.198 against 0.204 ms per 32^3
+    // evaluation; the FP64 one (160 VGPRs) is already at its occupancy limit
+    if (mixed) return launch_eval<kPairHome / 2>(s, a, mixed, cell_start, pq, list, list_cnt, cap, freal);
     return launch_eval<kPairHome>(s, a, mixed, cell_start, pq, list, list_cnt, cap, freal);
 }
 
