@@ -275,6 +275,12 @@ void enqueue(ewald_server_s *s, const std::vector<Request *> &rs, int st)
         (void)hipGetLastError();
         rc = EWALD_ERR_DEVICE;
     }
+    if (rc == EWALD_ERR_DEVICE) {
+        // part of the sequence may have been enqueued: let it finish before the
+        // workspace blocks return to the arena
+        (void)hipStreamSynchronize(stream);
+        (void)hipGetLastError();
+    }
     std::lock_guard<std::mutex> lk(s->mu);
     if (rc != EWALD_OK) {
         if (ev) s->events.push_back(ev);
