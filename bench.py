@@ -23,6 +23,8 @@ oracle's own throughput on this host.  Beside the headline:
 * ``cpu_baselines``: the FP64 oracle on this host's cores at every config
   (median of 3 runs where that stays short, one run for the 10^6-ion system)
   and single-threaded at the two smallest, with the CPU model;
+* ``batch``: 64 small systems (500-5000 ions) evaluated one by one and in
+  one batched launch sequence (ewald_energy_forces_batch);
 * ``serving``: the request server on a mix of 256 independent electrolyte
   systems (N = 500 ... 50000, K = 9 ... 41): its saturation throughput with
   small requests batched and one by one (and of the systems below 5,000 ions
@@ -326,6 +328,50 @@ def cpu_line(sysm, sec, threads, runs):
             f"one full FP64 oracle evaluation of the {sysm.n}-ion {sysm.name} workload"}
 
 
+def batched(n_systems=64):
+    """Many small systems (electrolytes of 500-5000 ions from the serving mix's
+    recipe) evaluated one by one through their plans against one
+    ewald_energy_forces_batch call: median wall time of 10 repetitions each."""
+    import torch
+
+    from paper_1708_01135_amd import ewald, workloads
+    mix = workloads.serving_mix(n_systems, seed=21, n_lo=500, n_hi=5000)
+    dev = torch.device("cuda:0")
+    res = {"systems": n_systems, "n_total": int(sum(it["n"] for it in mix)),
+           "n_range": [min(it["n"] for it in mix), max(it["n"] for it in mix)]}
+    for prec in ("mixed", "fp64"):
+        plans = [ewald.Plan(it["n"], it["box_L"], it["alpha"], it["r_c"], it["k_max"], prec) for it in mix]
+        items = [(p, torch.tensor(it["pos"], device=dev), torch.tensor(it["q"], device=dev),
+                  (torch.empty(5, dtype=torch.float64, device=dev),
+                   torch.empty((it["n"], 3), dtype=torch.float64, device=dev), None)) for p, it in zip(plans, mix)]
+
+        def one_by_one():
+            for p, a, b, o in items:
+                p.energy_forces(a, b, True, False, out=o)
+
+        def together():
+            ewald.energy_forces_batch(items)
+
+        out = {}
+        for name, fn in (("one_by_one_ms", one_by_one), ("batched_ms", together)):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(10):
+                t = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            out[name] = sorted(ts)[len(ts) // 2] * 1e3
+        out["batched_systems_per_s"] = n_systems / (out["batched_ms"] * 1e-3)
+        out["speedup"] = out["one_by_one_ms"] / out["batched_ms"]
+        res[prec] = out
+        for p in plans:
+            p.release()
+    return res
+
+
 def serving(n_systems, passes, express_cus=False):
     """Request server on independent electrolyte systems (density 0.8, r_c = 4.5,
     alpha r_c^2 = 14.4, K matched to the real-space exponent): saturation throughput
@@ -550,8 +596,10 @@ def main():
                 sec, used, _ = time_oracle(s, runs, threads=1)
                 cpus[f"{name}_1thread"] = cpu_line(s, sec, used, runs)
 
-    serve = None
+    serve = batch = None
     if not args.no_serving:
+        log("batched small systems")
+        batch = batched()
         log("serving mix")
         serve = serving(args.serving_systems, args.serving_passes, args.serving_express_cus)
     line = {
@@ -581,6 +629,7 @@ def main():
         "cpu_baselines": cpus or None,
         "host": host_info(),
         "configs": configs or None,
+        "batch": batch,
         "serving": serve,
         "bench_seconds": round(time.perf_counter() - t_start, 1),
     }

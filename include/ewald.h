@@ -115,9 +115,11 @@ enum {
  *                                        measure each kernel alone),
  *                EWALD_FLAG_NO_WORKSPACE allocate only the plan's constant tables
  *                                        (a few MB at most); such a plan is
- *                                        evaluated with ewald_energy_forces_noalloc()
- *                                        alone (every other evaluation and debug
- *                                        call returns EWALD_ERR_INVALID_ARG).
+ *                                        evaluated with ewald_energy_forces_noalloc(),
+ *                                        or with ewald_energy_forces_ws() and
+ *                                        ewald_energy_forces_batch() given a
+ *                                        workspace (every other evaluation and
+ *                                        debug call returns EWALD_ERR_INVALID_ARG).
  *              Other bits are invalid.  The vector kernels are
  *              also used where the matrix-core ones do not fit: the gather when a
  *              block's staged z powers would exceed 64 KB of LDS (FP64 with
@@ -244,11 +246,17 @@ ewald_status ewald_energy_forces_ws(ewald_plan_t plan, int64_t n, const double *
  *                        NULL: then the plan's own buffers are used, and that
  *                        plan (made without EWALD_FLAG_NO_WORKSPACE) is used
  *                        by no other NULL-workspace entry of the batch.
- *   stream               hipStream_t the whole batch is enqueued on (NULL: the
- *                        null stream); the plans' own streams are not used, so
- *                        no earlier call on a plan may still be running on
+ *   stream               hipStream_t the batch is enqueued on (NULL: the null
+ *                        stream).  As in a single evaluation, the
+ *                        reciprocal-space launches run beside the real-space
+ *                        ones on a second stream, that of plans[0], forked from
+ *                        and joined back to `stream` with plans[0]'s events,
+ *                        unless plans[0] was made with EWALD_FLAG_ONE_STREAM;
+ *                        work enqueued on `stream` afterwards sees the whole
+ *                        batch.  The plans' own streams are not used otherwise,
+ *                        so no earlier call on a plan may still be running on
  *                        another stream, and ewald_plan_status() is read after
- *                        synchronising this one.
+ *                        synchronising `stream`.
  * Each system's results are bitwise those of ewald_energy_forces_ws() on the
  * same inputs: every workgroup runs the same code on the same arguments.
  * Allocates nothing; the launch descriptors travel in the kernel arguments.

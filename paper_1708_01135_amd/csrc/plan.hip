@@ -791,21 +791,6 @@ ewald_status ewald_plan_set_stream(ewald_plan_t plan, void *stream)
 
 namespace {
 
-// The whole evaluation enqueued on stream s (the plan's stream, or its capture
-// stream while a graph is recorded).  energy_only skips the force gather (the
-// reciprocal energy comes from the structure factor alone); gscale, when
-// given, turns the force / dE/dq outputs into the adjoint.
-// Whether the real-space chain waits for the phase tables.  Started together,
-// the real-space kernels (tens of thousands of small blocks) take the compute
-// units from the phase kernel: at 10^6 ions it ran 3.6 ms beside them against
-// 0.47 ms alone, on the reciprocal chain that sets the wall time.  Where the
-// reciprocal work dominates, waiting costs the real-space chain little.  A pair
-// costs about 31 (particle, k) terms (32^3: 114 us for 1.25e7 pairs against
-// 157 us for 5.5e8 terms); the wait is taken when the reciprocal chain is
-// estimated at three times the real-space one or more: |K+| ~ (2/3) pi K^3
-// against 3 x 31 x (4/3) pi r_c^3 n / L^3 pairs per particle.  Measured: 10^6
-// ions (ratio 3.9) 24.4 against 25.5 ms mixed, 33.0 against 33.9 FP64; 64^3
-// (ratio 2.1) gained nothing mixed and lost 2 % in FP64, so it does not wait.
 // Position of a kernel class in the one-stream launch order (0: the workspace
 // clear that precedes it).  A batch launches its systems' kernels class by
 // class in this order.
@@ -818,6 +803,17 @@ int batch_rank(int kind)
     return rank[kind];
 }
 
+// Whether the real-space chain waits for the phase tables.  Started together,
+// the real-space kernels (tens of thousands of small blocks) take the compute
+// units from the phase kernel: at 10^6 ions it ran 3.6 ms beside them against
+// 0.47 ms alone, on the reciprocal chain that sets the wall time.  Where the
+// reciprocal work dominates, waiting costs the real-space chain little.  A pair
+// costs about 31 (particle, k) terms (32^3: 114 us for 1.25e7 pairs against
+// 157 us for 5.5e8 terms); the wait is taken when the reciprocal chain is
+// estimated at three times the real-space one or more: |K+| ~ (2/3) pi K^3
+// against 3 x 31 x (4/3) pi r_c^3 n / L^3 pairs per particle.  Measured: 10^6
+// ions (ratio 3.9) 24.4 against 25.5 ms mixed, 33.0 against 33.9 FP64; 64^3
+// (ratio 2.1) gained nothing mixed and lost 2 % in FP64, so it does not wait.
 bool phase_first(const ewald_params &prm, int64_t n)
 {
     const double L = prm.box_L, rc = prm.r_c, K = prm.k_max;
@@ -826,6 +822,10 @@ bool phase_first(const ewald_params &prm, int64_t n)
     return kvec > 3.0 * 31.0 * pairs;
 }
 
+// The whole evaluation enqueued on stream s (the plan's stream, or its capture
+// stream while a graph is recorded).  energy_only skips the force gather (the
+// reciprocal energy comes from the structure factor alone); gscale, when
+// given, turns the force / dE/dq outputs into the adjoint.
 ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_stream, int64_t n,
                          const double *pos, const double *q, double *energy, double *forces, double *dEdq,
                          const double *gscale, bool energy_only, bool allow_prof = true)
@@ -1205,10 +1205,33 @@ ewald_status ewald_energy_forces_batch(int32_t count, const ewald_plan_t *plans,
     });
     std::vector<unsigned char> pack;
     hipError_t e = hipSuccess;
+    // As in a single evaluation, the reciprocal-space classes run on a second
+    // stream (plans[0]'s), forked from and joined back to `stream`, beside the
+    // real-space ones, unless plans[0] keeps everything on one stream.
+    ewald_plan_t p0 = plans[0];
+    const bool two = (p0->prm.flags & EWALD_FLAG_ONE_STREAM) == 0;
+    bool forked = false, joined = false;
+    auto fork = [&] {
+        if (!two || forked || e != hipSuccess) return;
+        e = hipEventRecord(p0->ev_fork, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(p0->aux, p0->ev_fork, 0);
+        forked = true;
+    };
+    auto join = [&] {
+        if (!forked || joined || e != hipSuccess) return;
+        e = hipEventRecord(p0->ev_join, p0->aux);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, p0->ev_join, 0);
+        joined = true;
+    };
     for (size_t lo = 0; lo < order.size() && e == hipSuccess;) {
         size_t hi = lo;
         while (hi < order.size() && r[order[hi]].kind == r[order[lo]].kind && r[order[hi]].occ == r[order[lo]].occ)
             ++hi;
+        const int kind = r[order[lo]].kind;
+        if (kind >= batch_rank(KC_PHASE)) fork();
+        if (kind >= batch_rank(KC_FINAL_P)) join();
+        const bool recip = kind >= batch_rank(KC_PHASE) && kind < batch_rank(KC_BIN);
+        const hipStream_t ls = forked && !joined && recip ? p0->aux : s;
         std::vector<bool> done(hi - lo, false);
         for (size_t g = lo; g < hi && e == hipSuccess; ++g) {
             if (done[g - lo]) continue;
@@ -1243,11 +1266,12 @@ ewald_status ewald_energy_forces_batch(int32_t count, const ewald_plan_t *plans,
                     break;
                 }
                 void *argv[] = {pack.data()};
-                e = hipLaunchKernel(head.many, dim3((unsigned)blocks), dim3((unsigned)head.threads), argv, smem, s);
+                e = hipLaunchKernel(head.many, dim3((unsigned)blocks), dim3((unsigned)head.threads), argv, smem, ls);
             }
         }
         lo = hi;
     }
+    join();
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return EWALD_ERR_DEVICE;
