@@ -511,8 +511,8 @@ def main():
         calib_copy(args.calib_copy_mib)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: the library evaluates on exactly one GPU (--gpus 1); it has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
 
