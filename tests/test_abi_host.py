@@ -145,3 +145,13 @@ def test_server_without_gpu_reports_device_error():
     prm = ew.ServerParams(0, 4, ew.MIXED, 0, 0)
     h = ctypes.c_void_p()
     assert ew.library().ewald_server_create(ctypes.byref(prm), ctypes.byref(h)) == ew.ERR_DEVICE
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "exactly one GPU" in r.stderr and r.stdout == ""
