@@ -165,13 +165,15 @@ constexpr int kSmNap = 24;
 constexpr int kSmNapSmall = 12;  // the instance for KP <= 2 kSmNapSmall
 constexpr int kSmMaxKP = 2 * kSmNap;  // k_max + 1 <= KP <= kSmMaxKP
 constexpr int kSmStage = 9;  // staged entries per thread and buffer, a multiple of 3: 3 P KP <= kSmStage * kSmWaves * kLanes
-int sk_mfma_particles(int KP);
-size_t sk_mfma_smem_bytes(int KP);
+// (fp64: the plan's precision, which sets how much LDS the real-space kernels
+// beside it leave)
+int sk_mfma_particles(int KP, bool fp64);
+size_t sk_mfma_smem_bytes(int KP, bool fp64);
 inline int sk_mfma_row_blocks(int n_rows) { return (n_rows + kSmWaves * kSmTileRows - 1) / (kSmWaves * kSmTileRows); }
 // tile_of[block * kSmWaves + w]: the 16-row tile of wave w in row block `block`, or -1.
 hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx,
                           const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny, const int *row_m,
-                          const int *unit_base, const int *tile_of, d4 *part);
+                          const int *unit_base, const int *tile_of, d4 *part, bool fp64);
 // Particles per block of the matrix-core gather (16 per sub-tile): 32, or in
 // FP32 64 from 65536 particles on.  A block streams every coefficient of its
 // row split once, so 64 halves that traffic; below 65536 particles the

@@ -246,18 +246,21 @@ hipError_t KSkMfma<NMAX>::one(hipStream_t s, dim3 grid, int threads, size_t smem
 // two buffers take 2 x 3 P KP entries of LDS, and the structure factor runs
 // beside the real-space kernels, whose blocks need LDS on the same compute
 // units: P is the largest of 48, 40, 32, 24, 16, 8 whose two buffers stay
-// within 2 x 1792 entries (56 KiB), as long as that P is at least 24;
-// otherwise (large k_max) the largest P <= 32 whose tables fit kSmStage
+// within 2 x 1792 entries (56 KiB; 2 x 2304, 72 KiB, beside the FP64
+// real-space kernels, which hold fewer waves), as long as that P is at least
+// 24; otherwise (large k_max) the largest P <= 32 whose tables fit kSmStage
 // entries per thread, so that a step still holds enough quads to cover its
-// barrier.  Measured: rock salt 32^3 (k_max 20) took 0.203 ms per evaluation
-// with P = 24 and 0.211 with P = 48; rock salt 64^3 (k_max 32) 3.74 ms with
-// P = 32 and 4.18 with P = 8.  0 if even 8 particles do not fit.
-int sk_mfma_particles(int KP)
+// barrier.  Measured: rock salt 32^3 (k_max 20) took 0.199 ms per mixed
+// evaluation with P = 24, 0.204 with P = 32 and 0.211 with P = 48, and 0.257
+// ms per FP64 evaluation with P = 32 against 0.267 with P = 24; rock salt
+// 64^3 (k_max 32) 3.74 ms with P = 32 and 4.18 with P = 8.  0 if even 8
+// particles do not fit.
+int sk_mfma_particles(int KP, bool fp64)
 {
     static const int kCand[6] = {48, 40, 32, 24, 16, 8};
-    constexpr int kSmallStage = 1792;
+    const int small_stage = fp64 ? 2304 : 1792;
     for (int c = 0; c < 6; ++c)
-        if (3 * kCand[c] * KP <= kSmallStage) {
+        if (3 * kCand[c] * KP <= small_stage) {
             if (kCand[c] >= 24) return kCand[c];
             break;
         }
@@ -266,20 +269,23 @@ int sk_mfma_particles(int KP)
     return 0;
 }
 
-size_t sk_mfma_smem_bytes(int KP) { return (size_t)2 * 3 * sk_mfma_particles(KP) * KP * sizeof(c64); }
+size_t sk_mfma_smem_bytes(int KP, bool fp64)
+{
+    return (size_t)2 * 3 * sk_mfma_particles(KP, fp64) * KP * sizeof(c64);
+}
 
 hipError_t launch_sk_mfma(hipStream_t s, const RecipArgs &a, int n_chunks, int chunk_len, const c64 *tx,
                           const c64 *ty, const c64 *tz, const int *row_nx, const int *row_ny, const int *row_m,
-                          const int *unit_base, const int *tile_of, d4 *part)
+                          const int *unit_base, const int *tile_of, d4 *part, bool fp64)
 {
-    const int P = sk_mfma_particles(a.KP);
+    const int P = sk_mfma_particles(a.KP, fp64);
     const int n_rblocks = sk_mfma_row_blocks(a.n_rows);
     const dim3 grid(xcd_grid(n_rblocks * n_chunks));
     if (a.KP <= 2 * kSmNapSmall)
-        return launch(s, grid, kSmWaves * kLanes, sk_mfma_smem_bytes(a.KP),
+        return launch(s, grid, kSmWaves * kLanes, sk_mfma_smem_bytes(a.KP, fp64),
                       KSkMfma<kSmNapSmall>{a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx,
                                            row_ny, row_m, unit_base, tile_of, a.n_slots, part});
-    return launch(s, grid, kSmWaves * kLanes, sk_mfma_smem_bytes(a.KP),
+    return launch(s, grid, kSmWaves * kLanes, sk_mfma_smem_bytes(a.KP, fp64),
                   KSkMfma<kSmNap>{a.n, a.KP, P, a.n_rows, n_rblocks, n_chunks, chunk_len, tx, ty, tz, row_nx, row_ny,
                                   row_m, unit_base, tile_of, a.n_slots, part});
 }

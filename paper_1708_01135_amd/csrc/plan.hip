@@ -722,7 +722,7 @@ ewald_status ewald_plan(const ewald_params *params, ewald_plan_t *out)
     if (p->has_work) carve_work(cur, z, p->w);
     p->graphs = !(params->flags & EWALD_FLAG_NO_GRAPH);
     p->mfma_sk = !(params->flags & EWALD_FLAG_VALU_SK) && p->kl.KP <= kSmMaxKP &&
-                 sk_mfma_particles(p->kl.KP) >= 8;
+                 sk_mfma_particles(p->kl.KP, !p->mixed) >= 8;
     // the matrix-core gather stages a block's z powers in at most 64 KB of LDS
     // (its x^n, y^n tables come on top: at most 86 KB at k_max 83 in FP64)
     p->mfma_gather = !(params->flags & EWALD_FLAG_VALU_GATHER) &&
@@ -842,7 +842,8 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
         // most the partial-sum capacity, at least one staged tile per chunk
         int64_t c = sk_mfma_target_blocks() / sk_mfma_row_blocks(kl.n_rows);
         c = std::min<int64_t>(c, w.max_chunks);
-        c = std::min<int64_t>(c, (n + sk_mfma_particles(kl.KP) - 1) / sk_mfma_particles(kl.KP));
+        const int P = sk_mfma_particles(kl.KP, !p->mixed);
+        c = std::min<int64_t>(c, (n + P - 1) / P);
         n_chunks = (int)std::max<int64_t>(c, 1);
     }
     const int chunk_len = (int)((n + n_chunks - 1) / n_chunks);
@@ -888,7 +889,7 @@ ewald_status launch_path(ewald_plan_t p, const Work &w, hipStream_t s, bool one_
         run(ax, KC_SK, [&] {
             if (p->mfma_sk)
                 return launch_sk_mfma(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->row_nx, p->row_ny,
-                                      p->row_m, p->unit_base, p->sk_tile_of, w.part);
+                                      p->row_m, p->unit_base, p->sk_tile_of, w.part, !p->mixed);
             return launch_sk(ax, ra, n_chunks, chunk_len, tx, ty, tz, p->unit_g, p->unit_s, p->row_nx, p->row_ny,
                              w.part);
         });
@@ -1423,7 +1424,7 @@ ewald_status ewald_debug_stats_read(ewald_plan_t p, int64_t n, ewald_debug_stats
         int64_t naps = 0;
         for (int t : kl.sk_tile_of)
             if (t >= 0) naps += (kl.row_m[(size_t)t * kSmTileRows] + 2) / 2;
-        const int P = sk_mfma_particles(kl.KP);
+        const int P = sk_mfma_particles(kl.KP, !p->mixed);
         int64_t c = sk_mfma_target_blocks() / sk_mfma_row_blocks(kl.n_rows);
         c = std::min<int64_t>(c, p->w.max_chunks);
         c = std::min<int64_t>(c, (n + P - 1) / P);
