@@ -180,3 +180,34 @@ def test_batch_rejects_bad_arguments():
         a, b = ew.energy_forces_batch([(pn, pd, qd, _out(200)), (pn, pd, qd, _out(200))], [w1, w2])
         torch.cuda.synchronize()
         assert all(np.array_equal(x.cpu().numpy(), y.cpu().numpy()) for x, y in zip(a, b))
+
+
+@pytest.mark.timeout(600)
+def test_batch_with_optional_outputs_left_out():
+    # forces and dE/dq are optional per system: the energies and the outputs
+    # that are asked for equal those of the same systems evaluated alone
+    import torch
+    from paper_1708_01135_amd import ewald as ew
+    systems = _systems()[:6]
+    inputs = _inputs(systems)
+    plans = [ew.Plan(s[0], s[1], s[2], s[3], s[4], s[5]) for s in systems]
+    try:
+        alone = []
+        for p, (_, _, pd, qd) in zip(plans, inputs):
+            alone.append(_np(p.energy_forces(pd, qd, True, True)))
+            torch.cuda.synchronize()
+        items = []
+        for i, (p, s, (_, _, pd, qd)) in enumerate(zip(plans, systems, inputs)):
+            e, f, g = _out(s[0])
+            items.append((p, pd, qd, (e, f if i % 2 == 0 else None, g if i % 3 == 0 else None)))
+        got = ew.energy_forces_batch(items)
+        torch.cuda.synchronize()
+        for i, (e, f, g) in enumerate(got):
+            assert np.array_equal(e.cpu().numpy(), alone[i][0]), i
+            if f is not None:
+                assert np.array_equal(f.cpu().numpy(), alone[i][1]), i
+            if g is not None:
+                assert np.array_equal(g.cpu().numpy(), alone[i][2]), i
+    finally:
+        for p in plans:
+            p.release()
