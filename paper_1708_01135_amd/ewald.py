@@ -407,6 +407,7 @@ def energy_forces_batch(items, workspaces=None):
     tensor per item (or None entries) of at least
     ``plan.eval_workspace_bytes(n)`` bytes.  Enqueued on torch's current
     stream; returns the list of ``out``."""
+    import torch
     count = len(items)
     if not 1 <= count <= BATCH_MAX:
         raise ValueError(f"a batch holds 1 .. {BATCH_MAX} systems")
@@ -415,7 +416,6 @@ def energy_forces_batch(items, workspaces=None):
     pos_a, q_a, e_a, f_a, g_a, w_a = ((vp * count)() for _ in range(6))
     wb = (ctypes.c_size_t * count)()
     for i, (plan, pos, q, out) in enumerate(items):
-        import torch
         n = int(q.shape[0])
         for name, t, shape in (("pos", pos, (n, 3)), ("q", q, (n,))):
             if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
