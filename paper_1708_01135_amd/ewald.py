@@ -207,6 +207,20 @@ def _stream_handle(stream=None) -> int:
     return int(s.cuda_stream)
 
 
+def _check_outputs(out, n):
+    """Caller-given outputs (energy[5], forces (n,3) or None, dEdq (n,) or
+    None): contiguous float64 device tensors of exactly those shapes, since the
+    kernels write through their pointers."""
+    import torch
+    e, f, g = out
+    for name, t, shape in (("energy", e, (5,)), ("forces", f, (n, 3)), ("dEdq", g, (n,))):
+        if t is None and name != "energy":
+            continue
+        if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+    return e, f, g
+
+
 class Plan:
     """One Ewald plan: box, splitting, cutoffs, capacity and precision fixed.
 
@@ -250,7 +264,7 @@ class Plan:
             f = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if forces else None
             g = torch.empty(n, dtype=torch.float64, device=pos.device) if dEdq else None
         else:
-            e, f, g = out
+            e, f, g = _check_outputs(out, n)
         st = lib.ewald_plan_set_stream(self.handle, _stream_handle())
         if st != OK:
             raise EwaldError(st, "ewald_plan_set_stream")
@@ -270,7 +284,7 @@ class Plan:
         tensor of at least ``eval_workspace_bytes(n)`` bytes, 256-byte aligned);
         ``out`` = (energy[5], forces (n,3) or None, dEdq (n,) or None)."""
         n = self._check_inputs(pos, q)
-        e, f, g = out
+        e, f, g = _check_outputs(out, n)
         nbytes = workspace.numel() * workspace.element_size()
         st = _load().ewald_energy_forces_ws(self.handle, n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
                                             f.data_ptr() if f is not None else None,
@@ -283,14 +297,8 @@ class Plan:
         """The allocation-free evaluation: ``out`` = (energy[5], forces (n,3) or
         None, dEdq (n,) or None), preallocated float64 device tensors, is
         overwritten; the library's static scratch holds every other buffer."""
-        import torch
         n = self._check_inputs(pos, q)
-        e, f, g = out
-        for name, t, shape in (("energy", e, (5,)), ("forces", f, (n, 3)), ("dEdq", g, (n,))):
-            if t is None and name != "energy":
-                continue
-            if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
-                raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
+        e, f, g = _check_outputs(out, n)
         st = _load().ewald_energy_forces_noalloc(self.handle, n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
                                                  f.data_ptr() if f is not None else None,
                                                  g.data_ptr() if g is not None else None)
@@ -420,7 +428,7 @@ def energy_forces_batch(items, workspaces=None):
         for name, t, shape in (("pos", pos, (n, 3)), ("q", q, (n,))):
             if t.dtype != torch.float64 or not t.is_cuda or tuple(t.shape) != shape or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous float64 device tensor of shape {shape}")
-        e, f, g = out
+        e, f, g = _check_outputs(out, n)
         plans[i], ns[i] = plan.handle, n
         pos_a[i], q_a[i], e_a[i] = pos.data_ptr(), q.data_ptr(), e.data_ptr()
         f_a[i] = f.data_ptr() if f is not None else None
@@ -539,7 +547,7 @@ class Server:
             f = torch.empty((n, 3), dtype=torch.float64, device=pos.device) if forces else None
             g = torch.empty(n, dtype=torch.float64, device=pos.device) if dEdq else None
         else:
-            e, f, g = out
+            e, f, g = _check_outputs(out, n)
         t = ctypes.c_int64(-1)
         st = _load().ewald_server_submit(self.handle, int(sid), n, pos.data_ptr(), q.data_ptr(), e.data_ptr(),
                                          f.data_ptr() if f is not None else None,

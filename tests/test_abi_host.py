@@ -155,3 +155,14 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr and r.stdout == ""
+
+
+def test_binding_rejects_mis_shaped_outputs_without_gpu():
+    # caller-given outputs are checked before any pointer reaches the library
+    import torch
+    n = 10
+    e = torch.empty(5, dtype=torch.float64)  # host tensor: not a device tensor
+    with pytest.raises(ValueError):
+        ew._check_outputs((e, None, None), n)
+    with pytest.raises(ValueError):
+        ew._check_outputs((torch.empty(4, dtype=torch.float64), None, None), n)
