@@ -466,6 +466,11 @@ __device__ __forceinline__ void pair_body(int bx, int by, int64_t n, int nc, dou
             const bool ok = r + u * kSub < cnt_l;
             p[u] = pq[ok ? (e[u] & ((1u << kPairIndexBits) - 1)) : 0];
         }
+        // mixed: keep the first entry's two loads here, in flight with the
+        // others, rather than sunk into its predicated block (measured: the
+        // kernel 65 against 66.5 us at 32^3, 476 against 493 us at 64^3; the
+        // FP64 kernel gained nothing)
+        if constexpr (MIXED) asm volatile("" ::"v"(p[0].a), "v"(p[0].b), "v"(p[0].c), "v"(p[0].d), "v"(e[0]));
         // FP64: entries without an image shift (every entry, in most waves) skip
         // the shift lookup; (x - 0) - y is x - y exactly, so results do not
         // change.  (In the mixed kernel the second copy of the loop cost more
