@@ -128,3 +128,17 @@ def test_crowded_cell_sorted_in_lds(precision):
     again, _ = run_with_stats(pos, q, L, a, rc, K, precision)
     for x, y in zip(got, again):
         assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+@pytest.mark.parametrize("precision", PRECISIONS)
+@pytest.mark.parametrize("n, L", [(240, 9.0), (900, 12.0), (2000, 15.0), (3800, 18.0)])
+def test_small_system_list_splits_find_every_pair(n, L, precision):
+    # from a few hundred to a few thousand ions the list pass spreads each work
+    # item's home particles over 8, 4 or 2 waves: the lists must still hold
+    # every pair inside r_c exactly once, and the results match the oracle
+    a, rc, K = 0.8, 4.0, 10
+    pos, q = wl.random_neutral(n, L, seed=n)
+    got, stats = run_with_stats(pos, q, L, a, rc, K, precision)
+    compare(got, oracle.energy_forces(pos, q, L, a, rc, K, oracle.FAST), precision, f"n={n}")
+    assert stats["direct_particles"] == 0
+    assert stats["listed_pairs"] == brute_force_pairs(pos, L, rc)
