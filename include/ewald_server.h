@@ -16,9 +16,9 @@
  *     stream, stream 0, so that it never queues behind a large one, and any
  *     other request to the stream with the least outstanding estimated work
  *     among the rest (with one stream, everything goes to it);
- *   - a stream takes at most 2 launch sequences at a time; the rest wait in
- *     the dispatcher, where a small request that arrives later still passes
- *     them;
+ *   - the express stream (or the only stream) takes at most 2 launch
+ *     sequences at a time and each bulk stream 1; the rest wait in the
+ *     dispatcher, where a small request that arrives later still passes them;
  *   - the small requests that can start together (their workspaces fit, the
  *     express stream has a slot) go out as one batched launch sequence
  *     (ewald_energy_forces_batch: each kernel launched once over a ragged work
